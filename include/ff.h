@@ -1,0 +1,172 @@
+/*
+ * ff.h -- C ABI of the MI355X force-field minimization library (libff_mi355x.so).
+ *
+ * The library evaluates the macromolecular force field of section 2 of
+ * "Algorithms for local minimization of the force field for 3D
+ * macromolecules" (arXiv 1810.03358) -- harmonic bond stretch and angle bend,
+ * OPLS torsion, Coulomb and 12-6 Lennard-Jones with geometric mixing over all
+ * non-excluded atom pairs -- together with its gradient, and minimizes it
+ * locally from a given start (the problem statement at the end of section 2)
+ * with the first-order methods of section 5.1 and the line searches of
+ * section 5.2.  Everything after the start point is on the GPU: the host only
+ * launches work and polls a completion flag.
+ *
+ * Conventions shared by every entry point
+ *  - Units: Angstrom, radians, elementary charges, kcal/mol.  The Coulomb
+ *    constant is a field of ff_system (332.0715989 kcal A/(mol e^2) is the
+ *    paper's 1389.38757 kJ value expressed in kcal).
+ *  - Coordinates and gradients are FP64 arrays [n_atoms][3] (x, y, z of atom
+ *    0, then atom 1, ...), in DEVICE memory.
+ *  - The caller owns all memory.  The library never allocates device memory:
+ *    every device buffer it uses lives in the caller's workspace (size from
+ *    ff_workspace_bytes, device memory, 256-byte aligned).  The only host
+ *    allocation is the small ff_ctx object.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
+ *    One context serves one stream at a time; calls on one context must not
+ *    overlap.
+ *  - Errors: a negative ff_status means nothing was computed; ff_last_error()
+ *    returns a thread-local description.  Termination reasons of a
+ *    minimization are not errors (ff_min_result.term).
+ */
+#ifndef FF_MI355X_H
+#define FF_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FF_OK = 0,
+    FF_ERR_ARG = -1,          /* bad pointer, size, index, parameter */
+    FF_ERR_HIP = -2,          /* a HIP runtime call failed */
+    FF_ERR_WORKSPACE = -3,    /* workspace too small or misaligned */
+    FF_ERR_UNSUPPORTED = -4   /* valid input outside what this build handles */
+} ff_status;
+
+/* Methods of section 5.1: steepest descent with a line search (section 4,
+ * eq. 4), FGM (Algorithm 1), CG with the Polak-Ribiere-Polyak beta
+ * (Algorithm 2), L-BFGS (Algorithms 3 and 4). */
+typedef enum { FF_GD = 0, FF_FGM = 1, FF_CG = 2, FF_LBFGS = 3 } ff_method;
+
+/* Arithmetic of the pair sum.  FF_FP64: FP64 throughout.  FF_FP32_ACC64:
+ * pair terms in FP32 on double-single coordinate differences, accumulated
+ * in FP64 per tile; bonded terms, reductions and every optimizer decision in
+ * FP64 (section 5.3 runs the paper's library in single precision). */
+typedef enum { FF_FP64 = 0, FF_FP32_ACC64 = 1 } ff_precision;
+
+/* Why a minimization stopped. */
+typedef enum {
+    FF_CONVERGED = 0,         /* |grad E|_inf < tol at the returned point */
+    FF_MAX_ITER = 1,          /* max_iter iterations done */
+    FF_LS_FAILED = 2,         /* no relaxing step even after the restart
+                                 (the "dead end" of section 5.1) */
+    FF_NONFINITE_START = 3    /* E or grad E not finite at the start point */
+} ff_term;
+
+/* Line searches of section 5.2: LS_PAR (Algorithm 6), LS_H (Algorithm 5). */
+typedef enum { FF_LS_DEFAULT = -1, FF_LS_PAR = 0, FF_LS_H = 1 } ff_linesearch;
+
+/* ff_min_params.flags */
+#define FF_MIN_RESUME      1  /* continue from the state a previous ff_minimize
+                                 left in this context (same method, m and
+                                 precision; x must be that call's output) */
+#define FF_MIN_NO_CERTIFY  2  /* skip the closing FP64 evaluation (FP32 mode) */
+
+/* System description: HOST pointers, read only during ff_create.
+ * Angles are (i, vertex, k).  Excluded pairs are the bonded pairs and the
+ * outer atoms of every angle; 1-4 pairs interact at full strength; there is
+ * no cutoff.  This build requires every excluded pair (i, j) to satisfy
+ * |i - j| <= 64 (FF_ERR_UNSUPPORTED otherwise). */
+typedef struct {
+    int32_t n_atoms;
+    const double *q, *sigma, *eps;                      /* [n_atoms] e, A, kcal/mol */
+    int32_t n_bonds;
+    const int32_t *bond;                                /* [n_bonds][2] */
+    const double *bond_k, *bond_r0;                     /* [n_bonds] E = K (r - r0)^2 */
+    int32_t n_angles;
+    const int32_t *angle;                               /* [n_angles][3] */
+    const double *angle_k, *angle_t0;                   /* [n_angles] E = K (theta - theta0)^2 */
+    int32_t n_dihedrals;
+    const int32_t *dihedral;                            /* [n_dihedrals][4] */
+    const double *dihedral_v;                           /* [n_dihedrals][4] V1..V4 */
+    double coulomb_c;                                   /* kcal A / (mol e^2) */
+} ff_system;
+
+/* Minimizer parameters (host struct).  ff_default_params fills the defaults
+ * given in brackets. */
+typedef struct {
+    int32_t method;       /* ff_method [FF_LBFGS] */
+    int32_t m;            /* L-BFGS memory, 1..32 [10] */
+    double tol;           /* stop when |grad E|_inf < tol, kcal/mol/A, > 0 [1e-3] */
+    int32_t max_iter;     /* >= 0 [2000] */
+    int32_t precision;    /* ff_precision [FF_FP64] */
+    int32_t linesearch;   /* ff_linesearch [FF_LS_DEFAULT: LS_H for FGM, else LS_PAR] */
+    int32_t ls_K;         /* LS_PAR trial count, 2..8 [2] */
+    double h_init;        /* first step along the unit direction, A [0.1] */
+    double k_plus;        /* LS growth factor > 1 [2] */
+    double k_minus;       /* LS shrink factor in (0,1) [0.5] */
+    double eps_h;         /* LS_H gives up below this step, A [1e-10] */
+    int32_t cg_restart;   /* CG restarts from -g every cg_restart iterations; 0: 3N [0] */
+    int32_t flags;        /* FF_MIN_* [0] */
+} ff_min_params;
+
+/* Outcome of ff_minimize (host struct). */
+typedef struct {
+    int32_t term;         /* ff_term */
+    int32_t iters;        /* accepted iterations */
+    int32_t evals;        /* energy+gradient evaluations (all precisions) */
+    int32_t evals_fp64;   /* of which in FP64 */
+    double energy;        /* E at the returned point (FP64 unless NO_CERTIFY) */
+    double grad_inf;      /* |grad E|_inf there */
+    double grad_2;        /* |grad E|_2 there */
+} ff_min_result;
+
+typedef struct ff_ctx ff_ctx;   /* opaque host object bound to one workspace */
+
+/* Bytes of device workspace a system needs; m_max is the largest L-BFGS
+ * memory ff_minimize will be asked for (0 if only ff_energy_grad is used).
+ * Returns 0 on invalid input. */
+size_t ff_workspace_bytes(const ff_system *sys, int32_t m_max);
+
+/* Validate the system (indices in range, sizes, exclusion window), pack its
+ * parameters and topology into the workspace and return a context.  Blocks
+ * until the upload on `stream` is done. */
+ff_status ff_create(const ff_system *sys, void *workspace, size_t workspace_bytes,
+                    int32_t m_max, void *stream, ff_ctx **out);
+
+/* Release the host context (the workspace stays the caller's). */
+ff_status ff_destroy(ff_ctx *ctx);
+
+/* E(x) and grad E(x) of section 2 at xyz (device, [n_atoms][3]).  energy:
+ * device pointer to one double; grad: device [n_atoms][3] or NULL.  Enqueued
+ * on `stream`, returns without waiting.  A clash gives IEEE inf/NaN values,
+ * not an error. */
+ff_status ff_energy_grad(ff_ctx *ctx, const double *xyz, double *energy, double *grad,
+                         int32_t precision, void *stream);
+
+/* Local minimization from xyz_inout (device, [n_atoms][3]); on return it
+ * holds the result point: the last iterate for GD, CG and L-BFGS, the best
+ * iterate for FGM (Algorithm 1).  Blocks until done. */
+ff_status ff_minimize(ff_ctx *ctx, double *xyz_inout, const ff_min_params *params,
+                      ff_min_result *result, void *stream);
+
+/* Per-iteration trace of the last ff_minimize on this context, for
+ * diagnostics and tests: host_out[3k .. 3k+2] = (E after iteration k, the
+ * accepted step h, evaluations done so far), up to max_entries (the library
+ * keeps the first 4096 iterations of a call).  Returns the number of entries
+ * written or a negative ff_status.  Blocks on `stream`. */
+int32_t ff_get_trace(ff_ctx *ctx, double *host_out, int32_t max_entries, void *stream);
+
+/* Fill the defaults listed in ff_min_params. */
+void ff_default_params(ff_min_params *params);
+
+/* Thread-local text of the last error ("" if none). */
+const char *ff_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FF_MI355X_H */

@@ -1,0 +1,150 @@
+"""MI355X force-field energy/gradient and local minimization (arXiv 1810.03358).
+
+Thin Python binding of the C ABI in ``include/ff.h``: argument marshalling
+only.  Every evaluation and every optimizer step runs in the HIP kernels of
+``libff_mi355x.so``; PyTorch supplies device memory and the stream.  Nothing
+here computes the force field or takes an optimizer decision, and there is no
+CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import (  # noqa: F401
+    FF_GD, FF_FGM, FF_CG, FF_LBFGS, FF_FP64, FF_FP32_ACC64,
+    FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START,
+    FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H, FF_MIN_RESUME, FF_MIN_NO_CERTIFY,
+    FF_OK, FF_ERR_ARG, FF_ERR_HIP, FF_ERR_WORKSPACE, FF_ERR_UNSUPPORTED,
+)
+
+METHODS = {"gd": FF_GD, "fgm": FF_FGM, "cg": FF_CG, "lbfgs": FF_LBFGS}
+PRECISIONS = {"fp64": FF_FP64, "fp32": FF_FP32_ACC64}
+TERMS = {FF_CONVERGED: "converged", FF_MAX_ITER: "max_iter", FF_LS_FAILED: "ls_failed",
+         FF_NONFINITE_START: "nonfinite_start"}
+
+
+class FFError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where} failed with status {status}: {N.last_error()}")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != FF_OK:
+        raise FFError(status, where)
+
+
+class HostSystem:
+    """ff_system view of a system dict (host arrays kept alive here)."""
+
+    def __init__(self, d: dict):
+        f64 = lambda k: np.ascontiguousarray(d[k], dtype=np.float64).ravel()  # noqa: E731
+        i32 = lambda k: np.ascontiguousarray(d[k], dtype=np.int32).ravel()  # noqa: E731
+        self.arrays = dict(q=f64("q"), sigma=f64("sigma"), eps=f64("eps"),
+                           bond=i32("bonds"), bond_k=f64("bond_k"), bond_r0=f64("bond_r0"),
+                           angle=i32("angles"), angle_k=f64("angle_k"), angle_t0=f64("angle_t0"),
+                           dihedral=i32("dihedrals"), dihedral_v=f64("dihedral_v"))
+        a = self.arrays
+        dp = lambda v: v.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        ip = lambda v: v.ctypes.data_as(C.POINTER(C.c_int32))  # noqa: E731
+        self.n = int(d["n_atoms"])
+        self.c = N.FFSystem(self.n, dp(a["q"]), dp(a["sigma"]), dp(a["eps"]),
+                            len(a["bond_k"]), ip(a["bond"]), dp(a["bond_k"]), dp(a["bond_r0"]),
+                            len(a["angle_k"]), ip(a["angle"]), dp(a["angle_k"]), dp(a["angle_t0"]),
+                            len(a["dihedral"]) // 4, ip(a["dihedral"]), dp(a["dihedral_v"]),
+                            float(d["coulomb_c"]))
+
+
+def workspace_bytes(system: dict, m_max: int = 10) -> int:
+    return int(N.load().ff_workspace_bytes(C.byref(HostSystem(system).c), m_max))
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A prepared system on one GPU: workspace (torch uint8 tensor) + ff_ctx."""
+
+    def __init__(self, system: dict, m_max: int = 10, device="cuda", stream=None):
+        lib = N.load()
+        self.host = HostSystem(system)
+        self.n = self.host.n
+        self.device = torch.device(device)
+        nbytes = int(lib.ff_workspace_bytes(C.byref(self.host.c), m_max))
+        if nbytes == 0:
+            raise FFError(FF_ERR_ARG, "ff_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        ctx = C.c_void_p()
+        _check(lib.ff_create(C.byref(self.host.c), C.c_void_p(self._ws_ptr), nbytes, m_max,
+                             _stream_ptr(stream), C.byref(ctx)), "ff_create")
+        self._ctx = ctx
+        self.m_max = m_max
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            N.load().ff_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _coords(self, x) -> torch.Tensor:
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()
+                and x.numel() == 3 * self.n):
+            raise ValueError("coordinates must be a contiguous float64 CUDA tensor with 3*n_atoms elements")
+        return x
+
+    def energy_grad(self, x: torch.Tensor, precision: str | int = "fp64", want_grad: bool = True,
+                    out_e: torch.Tensor | None = None, out_g: torch.Tensor | None = None, stream=None):
+        """E and grad E at x (device tensor [n_atoms, 3], float64).  Asynchronous
+        on the current stream; returns device tensors."""
+        x = self._coords(x)
+        prec = PRECISIONS.get(precision, precision)
+        e = out_e if out_e is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+        g = (out_g if out_g is not None else torch.empty_like(x)) if want_grad else None
+        _check(N.load().ff_energy_grad(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(e.data_ptr()),
+                                       C.c_void_p(g.data_ptr()) if g is not None else None, int(prec),
+                                       _stream_ptr(stream)), "ff_energy_grad")
+        return e, g
+
+    def minimize(self, x: torch.Tensor, method: str | int = "lbfgs", m: int = 10, tol: float = 1e-3,
+                 max_iter: int = 2000, precision: str | int = "fp64", linesearch: int = FF_LS_DEFAULT,
+                 ls_K: int = 2, h_init: float = 0.1, k_plus: float = 2.0, k_minus: float = 0.5,
+                 eps_h: float = 1e-10, cg_restart: int = 0, resume: bool = False, certify: bool = True,
+                 stream=None) -> dict:
+        """Minimize in place (x is overwritten with the result point); blocks."""
+        x = self._coords(x)
+        p = N.FFMinParams()
+        N.load().ff_default_params(C.byref(p))
+        p.method = METHODS.get(method, method)
+        p.m, p.tol, p.max_iter = m, tol, max_iter
+        p.precision = PRECISIONS.get(precision, precision)
+        p.linesearch, p.ls_K = linesearch, ls_K
+        p.h_init, p.k_plus, p.k_minus, p.eps_h = h_init, k_plus, k_minus, eps_h
+        p.cg_restart = cg_restart
+        p.flags = (FF_MIN_RESUME if resume else 0) | (0 if certify else FF_MIN_NO_CERTIFY)
+        r = N.FFMinResult()
+        _check(N.load().ff_minimize(self._ctx, C.c_void_p(x.data_ptr()), C.byref(p), C.byref(r),
+                                    _stream_ptr(stream)), "ff_minimize")
+        return dict(term=r.term, term_name=TERMS.get(r.term, str(r.term)), iters=r.iters, evals=r.evals,
+                    evals_fp64=r.evals_fp64, energy=r.energy, grad_inf=r.grad_inf, grad_2=r.grad_2)
+
+    def trace(self, max_entries: int = 4096, stream=None) -> np.ndarray:
+        """(E, h, evals) after each iteration of the last minimize call."""
+        buf = np.zeros(3 * max_entries)
+        n = N.load().ff_get_trace(self._ctx, buf.ctypes.data_as(C.POINTER(C.c_double)), max_entries,
+                                  _stream_ptr(stream))
+        if n < 0:
+            raise FFError(n, "ff_get_trace")
+        return buf[: 3 * n].reshape(n, 3)

@@ -1,0 +1,84 @@
+"""ctypes declarations of the C ABI in include/ff.h (libff_mi355x.so)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libff_mi355x.so")
+
+FF_OK, FF_ERR_ARG, FF_ERR_HIP, FF_ERR_WORKSPACE, FF_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+FF_GD, FF_FGM, FF_CG, FF_LBFGS = 0, 1, 2, 3
+FF_FP64, FF_FP32_ACC64 = 0, 1
+FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START = 0, 1, 2, 3
+FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H = -1, 0, 1
+FF_MIN_RESUME, FF_MIN_NO_CERTIFY = 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class FFSystem(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("q", _dp), ("sigma", _dp), ("eps", _dp),
+        ("n_bonds", C.c_int32), ("bond", _ip), ("bond_k", _dp), ("bond_r0", _dp),
+        ("n_angles", C.c_int32), ("angle", _ip), ("angle_k", _dp), ("angle_t0", _dp),
+        ("n_dihedrals", C.c_int32), ("dihedral", _ip), ("dihedral_v", _dp),
+        ("coulomb_c", C.c_double),
+    ]
+
+
+class FFMinParams(C.Structure):
+    _fields_ = [
+        ("method", C.c_int32), ("m", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
+        ("precision", C.c_int32), ("linesearch", C.c_int32), ("ls_K", C.c_int32),
+        ("h_init", C.c_double), ("k_plus", C.c_double), ("k_minus", C.c_double), ("eps_h", C.c_double),
+        ("cg_restart", C.c_int32), ("flags", C.c_int32),
+    ]
+
+
+class FFMinResult(C.Structure):
+    _fields_ = [
+        ("term", C.c_int32), ("iters", C.c_int32), ("evals", C.c_int32), ("evals_fp64", C.c_int32),
+        ("energy", C.c_double), ("grad_inf", C.c_double), ("grad_2", C.c_double),
+    ]
+
+
+EXPORTS = ("ff_workspace_bytes", "ff_create", "ff_destroy", "ff_energy_grad", "ff_minimize",
+           "ff_get_trace", "ff_default_params", "ff_last_error")
+
+_lib = None
+
+
+def load():
+    """Load the HIP library; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1810_03358_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    lib.ff_workspace_bytes.argtypes = [C.POINTER(FFSystem), C.c_int32]
+    lib.ff_workspace_bytes.restype = C.c_size_t
+    lib.ff_create.argtypes = [C.POINTER(FFSystem), C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
+                              C.POINTER(C.c_void_p)]
+    lib.ff_create.restype = C.c_int
+    lib.ff_destroy.argtypes = [C.c_void_p]
+    lib.ff_destroy.restype = C.c_int
+    lib.ff_energy_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    lib.ff_energy_grad.restype = C.c_int
+    lib.ff_minimize.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(FFMinParams), C.POINTER(FFMinResult),
+                                C.c_void_p]
+    lib.ff_minimize.restype = C.c_int
+    lib.ff_get_trace.argtypes = [C.c_void_p, _dp, C.c_int32, C.c_void_p]
+    lib.ff_get_trace.restype = C.c_int32
+    lib.ff_default_params.argtypes = [C.POINTER(FFMinParams)]
+    lib.ff_default_params.restype = None
+    lib.ff_last_error.argtypes = []
+    lib.ff_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().ff_last_error().decode()

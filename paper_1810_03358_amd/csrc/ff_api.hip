@@ -1,0 +1,482 @@
+// Host side of the C ABI declared in include/ff.h: argument validation,
+// workspace layout, one-time packing of parameters and topology, and the
+// launch sequence of an evaluation or a minimization.
+//
+// A minimization is a fixed cycle of six kernels captured once into a HIP
+// graph: build the point (trial / direction / momentum) -> bonded terms ->
+// FP32 pair kernel -> FP64 pair kernel -> finalize (+ decision) -> accept
+// pass (+ decision).  Only
+// one of the two pair kernels does work in a cycle; the others return at
+// once when the control block says they have nothing to do.  The host
+// replays the graph and polls one completion flag.
+#include <algorithm>
+#include <cstdarg>
+#include <cstddef>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ff.h"
+#include "ff_internal.h"
+
+namespace ff {
+hipError_t launch_pair(const Args& a, int prec, hipStream_t s);
+hipError_t launch_bonded(const Args& a, hipStream_t s);
+hipError_t launch_finalize(const Args& a, hipStream_t s);
+hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s);
+hipError_t launch_kick(const Args& a, const MinParamsDev& p, int resume, double* trace, int trace_cap,
+                       hipStream_t s);
+hipError_t launch_reset(const Args& a, hipStream_t s);
+}  // namespace ff
+
+using namespace ff;
+
+struct ff_ctx {
+    Layout L;
+    char* ws;
+    int32_t* host_flag;          // pinned: done flag polled by ff_minimize
+    Ctl* host_ctl;               // pinned copy of the control block
+    hipGraphExec_t graph = nullptr;
+    hipStream_t own = nullptr;   // private stream: graph capture, and calls made on the NULL stream
+    int last_method = -1, last_m = -1, last_prec = -1;
+};
+
+static thread_local std::string g_err;
+
+static ff_status fail(ff_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(FF_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ layout
+static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
+    std::memset(&L, 0, sizeof L);
+    if (!s || s->n_atoms < 1 || s->n_bonds < 0 || s->n_angles < 0 || s->n_dihedrals < 0) return false;
+    if (m_max < 0 || m_max > kMaxM) return false;
+    L.n = s->n_atoms;
+    L.np = (L.n + kAtomAlign - 1) / kAtomAlign * kAtomAlign;
+    if (L.np <= 2048) { L.cfg = 0; L.block = 64; L.chunk = 2; }
+    else if (L.np <= 16384) { L.cfg = 1; L.block = 256; L.chunk = 4; }
+    else { L.cfg = 2; L.block = 512; L.chunk = 8; }
+    L.nb = L.np / L.block;
+    L.nt = L.np / kTile;
+    L.n_units = 0;
+    L.n_chunks = 0;
+    for (int b = 0; b < L.nb; ++b) {
+        const int t0 = b * L.block / kTile;
+        const int units = L.nt - t0;
+        L.n_units += units;
+        L.n_chunks += (units + L.chunk - 1) / L.chunk;
+    }
+    L.n_bonds = s->n_bonds;
+    L.n_angles = s->n_angles;
+    L.n_dihedrals = s->n_dihedrals;
+    L.n_terms_slots = 2 * L.n_bonds + 3 * L.n_angles + 4 * L.n_dihedrals;
+    const int n_terms = L.n_bonds + L.n_angles + L.n_dihedrals;
+    L.n_bonded_blocks = std::max(1, (n_terms + kBondedPerBlock - 1) / kBondedPerBlock);
+    L.n_fin_blocks = (L.n + kFinBlock - 1) / kFinBlock;
+    L.m_max = m_max;
+    L.vstride = (3 * (size_t)L.np + 31) / 32 * 32;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
+    const size_t np = L.np;
+    L.off_ctl = take(sizeof(Ctl));
+    L.off_c12 = take(np * 4);
+    L.off_c6 = take(np * 4);
+    L.off_q = take(np * 4);
+    L.off_c12d = take(np * 8);
+    L.off_c6d = take(np * 8);
+    L.off_qd = take(np * 8);
+    L.off_excl = take(np * 8);
+    L.off_chunks = take((size_t)L.n_chunks * sizeof(ChunkInfo));
+    L.off_rows = take((size_t)L.nb * sizeof(RowInfo));
+    L.off_pi = take((size_t)L.n_chunks * L.block * 3 * 8);
+    L.off_pj = take((size_t)L.n_units * kTile * 3 * 8);
+    L.off_ep = take((size_t)L.n_chunks * 8);
+    L.off_bond = take((size_t)L.n_bonds * 8);
+    L.off_bondp = take((size_t)L.n_bonds * 16);
+    L.off_angle = take((size_t)L.n_angles * 12);
+    L.off_anglep = take((size_t)L.n_angles * 16);
+    L.off_dih = take((size_t)L.n_dihedrals * 16);
+    L.off_dihp = take((size_t)L.n_dihedrals * 32);
+    L.off_fb = take((size_t)L.n_terms_slots * 24);
+    L.off_eb = take((size_t)L.n_bonded_blocks * 8);
+    L.off_inc_start = take((np + 1) * 4);
+    L.off_inc = take((size_t)L.n_terms_slots * 4);
+    const size_t vec_blocks = (3 * np + kFinBlock - 1) / kFinBlock;
+    L.off_red = take(std::max(vec_blocks * kMaxDots, (size_t)L.n_fin_blocks * 3) * 8);
+    L.off_vec = take((size_t)V_COUNT * L.vstride * 8 + (size_t)kTraceCap * 3 * 8);
+    L.total = o;
+    return true;
+}
+
+static double* trace_buffer(const ff_ctx* c) {
+    return at<double>(c->ws, c->L.off_vec) + (size_t)V_COUNT * c->L.vstride;
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+size_t ff_workspace_bytes(const ff_system* sys, int32_t m_max) {
+    Layout L;
+    if (!make_layout(sys, m_max, L)) return 0;
+    return L.total;
+}
+
+void ff_default_params(ff_min_params* p) {
+    if (!p) return;
+    p->method = FF_LBFGS;
+    p->m = 10;
+    p->tol = 1e-3;
+    p->max_iter = 2000;
+    p->precision = FF_FP64;
+    p->linesearch = FF_LS_DEFAULT;
+    p->ls_K = 2;
+    p->h_init = 0.1;
+    p->k_plus = 2.0;
+    p->k_minus = 0.5;
+    p->eps_h = 1e-10;
+    p->cg_restart = 0;
+    p->flags = 0;
+}
+
+const char* ff_last_error(void) { return g_err.c_str(); }
+
+ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_t m_max, void* stream,
+                    ff_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(FF_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!s) return fail(FF_ERR_ARG, "system is null");
+    const int n = s->n_atoms;
+    if (n < 1) return fail(FF_ERR_ARG, "n_atoms must be >= 1");
+    if (!s->q || !s->sigma || !s->eps) return fail(FF_ERR_ARG, "per-atom parameter arrays are null");
+    if ((s->n_bonds && (!s->bond || !s->bond_k || !s->bond_r0)) ||
+        (s->n_angles && (!s->angle || !s->angle_k || !s->angle_t0)) ||
+        (s->n_dihedrals && (!s->dihedral || !s->dihedral_v)))
+        return fail(FF_ERR_ARG, "topology arrays are null");
+    if (m_max < 0 || m_max > kMaxM) return fail(FF_ERR_ARG, "m_max must be in [0, %d]", kMaxM);
+    if (!(std::isfinite(s->coulomb_c))) return fail(FF_ERR_ARG, "coulomb_c is not finite");
+    if (s->coulomb_c < 0.0) return fail(FF_ERR_UNSUPPORTED, "negative coulomb_c");
+    Layout L;
+    if (!make_layout(s, m_max, L)) return fail(FF_ERR_ARG, "invalid sizes");
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(FF_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
+    if (ws_bytes < L.total) return fail(FF_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(s->q[i]) || !(s->sigma[i] >= 0.0) || !(s->eps[i] >= 0.0) || !std::isfinite(s->sigma[i]) ||
+            !std::isfinite(s->eps[i]))
+            return fail(FF_ERR_ARG, "bad parameters of atom %d (sigma, eps must be finite and >= 0)", i);
+    // exclusion bitmasks: bit d-1 of atom i marks the pair (i, i+d)
+    std::vector<uint64_t> excl(L.np, 0ull);
+    auto add_excl = [&](int i, int j) -> ff_status {
+        if (i == j) return fail(FF_ERR_ARG, "a bond or angle joins atom %d to itself", i);
+        const int lo = std::min(i, j), hi = std::max(i, j);
+        if (hi - lo > kExclWindow)
+            return fail(FF_ERR_UNSUPPORTED, "excluded pair (%d, %d) is more than %d atoms apart", lo, hi, kExclWindow);
+        excl[lo] |= 1ull << (hi - lo - 1);
+        return FF_OK;
+    };
+    for (int b = 0; b < s->n_bonds; ++b) {
+        const int i = s->bond[2 * b], j = s->bond[2 * b + 1];
+        if (i < 0 || i >= n || j < 0 || j >= n) return fail(FF_ERR_ARG, "bond %d has an atom index out of range", b);
+        if (!std::isfinite(s->bond_k[b]) || !std::isfinite(s->bond_r0[b])) return fail(FF_ERR_ARG, "bond %d parameters", b);
+        ff_status st = add_excl(i, j);
+        if (st) return st;
+    }
+    for (int a = 0; a < s->n_angles; ++a) {
+        const int* t = s->angle + 3 * a;
+        for (int k = 0; k < 3; ++k)
+            if (t[k] < 0 || t[k] >= n) return fail(FF_ERR_ARG, "angle %d has an atom index out of range", a);
+        if (t[0] == t[1] || t[1] == t[2]) return fail(FF_ERR_ARG, "angle %d repeats its vertex", a);
+        ff_status st = add_excl(t[0], t[2]);
+        if (st) return st;
+    }
+    for (int d = 0; d < s->n_dihedrals; ++d)
+        for (int k = 0; k < 4; ++k)
+            if (s->dihedral[4 * d + k] < 0 || s->dihedral[4 * d + k] >= n)
+                return fail(FF_ERR_ARG, "dihedral %d has an atom index out of range", d);
+
+    // per-atom factors: c12 = 2 sqrt(eps) sigma^6, c6 = 2 sqrt(eps) sigma^3, q^ = sqrt(C) q
+    const double sqc = std::sqrt(s->coulomb_c);
+    std::vector<float> c12f(L.np, 0.f), c6f(L.np, 0.f), qf(L.np, 0.f);
+    std::vector<double> c12d(L.np, 0.0), c6d(L.np, 0.0), qd(L.np, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const double se = 2.0 * std::sqrt(s->eps[i]);
+        const double s3 = s->sigma[i] * s->sigma[i] * s->sigma[i];
+        c12d[i] = se * s3 * s3;
+        c6d[i] = se * s3;
+        qd[i] = sqc * s->q[i];
+        c12f[i] = (float)c12d[i];
+        c6f[i] = (float)c6d[i];
+        qf[i] = (float)qd[i];
+    }
+    // tile tables
+    std::vector<ChunkInfo> chunks;
+    std::vector<RowInfo> rows(L.nb);
+    int unit = 0;
+    for (int b = 0; b < L.nb; ++b) {
+        const int t0 = b * L.block / kTile;
+        rows[b].unit_start = unit;
+        rows[b].t0 = t0;
+        rows[b].chunk_start = (int)chunks.size();
+        for (int t = t0; t < L.nt; t += L.chunk) {
+            ChunkInfo c;
+            c.row = b;
+            c.t_begin = t;
+            c.t_end = std::min(t + L.chunk, L.nt);
+            c.unit_base = unit + (t - t0);
+            chunks.push_back(c);
+        }
+        rows[b].n_chunks = (int)chunks.size() - rows[b].chunk_start;
+        unit += L.nt - t0;
+    }
+    // bonded topology and the incidence lists (term-slot indices per atom)
+    std::vector<int> bond(2 * (size_t)L.n_bonds), angle(3 * (size_t)L.n_angles), dih(4 * (size_t)L.n_dihedrals);
+    std::vector<double> bondp(2 * (size_t)L.n_bonds), anglep(2 * (size_t)L.n_angles), dihp(4 * (size_t)L.n_dihedrals);
+    std::vector<std::vector<int>> inc_lists(L.np);
+    for (int b = 0; b < L.n_bonds; ++b) {
+        for (int k = 0; k < 2; ++k) { bond[2 * b + k] = s->bond[2 * b + k]; inc_lists[bond[2 * b + k]].push_back(2 * b + k); }
+        bondp[2 * b] = s->bond_k[b];
+        bondp[2 * b + 1] = s->bond_r0[b];
+    }
+    const int abase = 2 * L.n_bonds, dbase = abase + 3 * L.n_angles;
+    for (int a = 0; a < L.n_angles; ++a) {
+        for (int k = 0; k < 3; ++k) { angle[3 * a + k] = s->angle[3 * a + k]; inc_lists[angle[3 * a + k]].push_back(abase + 3 * a + k); }
+        anglep[2 * a] = s->angle_k[a];
+        anglep[2 * a + 1] = s->angle_t0[a];
+    }
+    for (int d = 0; d < L.n_dihedrals; ++d)
+        for (int k = 0; k < 4; ++k) {
+            dih[4 * d + k] = s->dihedral[4 * d + k];
+            dihp[4 * d + k] = s->dihedral_v[4 * d + k];
+            inc_lists[dih[4 * d + k]].push_back(dbase + 4 * d + k);
+        }
+    std::vector<int> inc_start(L.np + 1, 0), inc;
+    inc.reserve(L.n_terms_slots);
+    for (int i = 0; i < L.np; ++i) {
+        inc_start[i] = (int)inc.size();
+        for (int v : inc_lists[i]) inc.push_back(v);
+    }
+    inc_start[L.np] = (int)inc.size();
+
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    HIP_TRY(up(L.off_c12, c12f.data(), c12f.size() * 4));
+    HIP_TRY(up(L.off_c6, c6f.data(), c6f.size() * 4));
+    HIP_TRY(up(L.off_q, qf.data(), qf.size() * 4));
+    HIP_TRY(up(L.off_c12d, c12d.data(), c12d.size() * 8));
+    HIP_TRY(up(L.off_c6d, c6d.data(), c6d.size() * 8));
+    HIP_TRY(up(L.off_qd, qd.data(), qd.size() * 8));
+    HIP_TRY(up(L.off_excl, excl.data(), excl.size() * 8));
+    HIP_TRY(up(L.off_chunks, chunks.data(), chunks.size() * sizeof(ChunkInfo)));
+    HIP_TRY(up(L.off_rows, rows.data(), rows.size() * sizeof(RowInfo)));
+    HIP_TRY(up(L.off_bond, bond.data(), bond.size() * 4));
+    HIP_TRY(up(L.off_bondp, bondp.data(), bondp.size() * 8));
+    HIP_TRY(up(L.off_angle, angle.data(), angle.size() * 4));
+    HIP_TRY(up(L.off_anglep, anglep.data(), anglep.size() * 8));
+    HIP_TRY(up(L.off_dih, dih.data(), dih.size() * 4));
+    HIP_TRY(up(L.off_dihp, dihp.data(), dihp.size() * 8));
+    HIP_TRY(up(L.off_inc_start, inc_start.data(), inc_start.size() * 4));
+    HIP_TRY(up(L.off_inc, inc.data(), inc.size() * 4));
+    Args a{};
+    a.L = L;
+    a.ws = ws;
+    HIP_TRY(launch_reset(a, st));
+    HIP_TRY(hipStreamSynchronize(st));
+
+    ff_ctx* c = new ff_ctx();
+    c->L = L;
+    c->ws = ws;
+    void* hf = nullptr;
+    void* hc = nullptr;
+    if (hipHostMalloc(&hf, 256, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&hc, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        if (hf) (void)hipHostFree(hf);
+        delete c;
+        return fail(FF_ERR_HIP, "pinned host buffer allocation failed");
+    }
+    c->host_flag = (int32_t*)hf;
+    c->host_ctl = (Ctl*)hc;
+    if (hipStreamCreate(&c->own) != hipSuccess) {
+        (void)hipHostFree(hf);
+        (void)hipHostFree(hc);
+        delete c;
+        return fail(FF_ERR_HIP, "stream creation failed");
+    }
+    *out = c;
+    return FF_OK;
+}
+
+ff_status ff_destroy(ff_ctx* c) {
+    if (!c) return FF_OK;
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    (void)hipHostFree(c->host_flag);
+    (void)hipHostFree(c->host_ctl);
+    delete c;
+    return FF_OK;
+}
+
+ff_status ff_energy_grad(ff_ctx* c, const double* xyz, double* energy, double* grad, int32_t precision,
+                         void* stream) {
+    g_err.clear();
+    if (!c) return fail(FF_ERR_ARG, "context is null");
+    if (!xyz || !energy) return fail(FF_ERR_ARG, "xyz and energy must be device pointers");
+    if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
+    hipStream_t st = (hipStream_t)stream;
+    Args a{};
+    a.L = c->L;
+    a.ws = c->ws;
+    a.xyz_in = xyz;
+    a.e_out = energy;
+    a.g_out = grad;
+    a.direct = 1;
+    a.direct_prec = precision;
+    HIP_TRY(launch_bonded(a, st));
+    HIP_TRY(launch_pair(a, precision, st));
+    HIP_TRY(launch_finalize(a, st));
+    return FF_OK;
+}
+
+static ff_status build_graph(ff_ctx* c) {
+    hipStream_t st = c->own;
+    Args a{};
+    a.L = c->L;
+    a.ws = c->ws;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_cycle_vec(a, 0, st);
+    if (e == hipSuccess) e = launch_bonded(a, st);
+    if (e == hipSuccess) e = launch_pair(a, 1, st);
+    if (e == hipSuccess) e = launch_pair(a, 0, st);
+    if (e == hipSuccess) e = launch_finalize(a, st);
+    if (e == hipSuccess) e = launch_cycle_vec(a, 1, st);
+    hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess) return fail(FF_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(FF_ERR_HIP, "graph capture end: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { c->graph = nullptr; return fail(FF_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
+    return FF_OK;
+}
+
+ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_result* res, void* stream) {
+    g_err.clear();
+    if (!c || !xyz || !p || !res) return fail(FF_ERR_ARG, "null argument");
+    if (p->method < FF_GD || p->method > FF_LBFGS) return fail(FF_ERR_ARG, "bad method %d", p->method);
+    if (p->method == FF_LBFGS && (p->m < 1 || p->m > c->L.m_max))
+        return fail(FF_ERR_ARG, "m = %d outside [1, m_max = %d]", p->m, c->L.m_max);
+    if (!(p->tol > 0.0)) return fail(FF_ERR_ARG, "tol must be > 0");
+    if (p->max_iter < 0) return fail(FF_ERR_ARG, "max_iter must be >= 0");
+    if (p->precision != FF_FP64 && p->precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision");
+    if (p->linesearch < -1 || p->linesearch > 1) return fail(FF_ERR_ARG, "bad line search");
+    if (p->ls_K < 2 || p->ls_K > kMaxLsTrials) return fail(FF_ERR_ARG, "ls_K must be in [2, %d]", kMaxLsTrials);
+    if (!(p->h_init > 0.0) || !(p->k_plus > 1.0) || !(p->k_minus > 0.0 && p->k_minus < 1.0) || !(p->eps_h > 0.0))
+        return fail(FF_ERR_ARG, "bad line-search constants");
+    if (p->cg_restart < 0) return fail(FF_ERR_ARG, "cg_restart must be >= 0");
+    const bool resume = (p->flags & FF_MIN_RESUME) != 0;
+    if (resume && (c->last_method != p->method || c->last_m != p->m || c->last_prec != p->precision))
+        return fail(FF_ERR_ARG, "resume needs the same method, m and precision as the previous call");
+    // a HIP graph cannot be captured on the NULL stream: such calls run on the
+    // context's own (blocking) stream, which orders itself after NULL-stream work
+    hipStream_t st = stream ? (hipStream_t)stream : c->own;
+    const Layout& L = c->L;
+    Args a{};
+    a.L = L;
+    a.ws = c->ws;
+    MinParamsDev d{};
+    d.method = p->method;
+    d.m = p->method == FF_LBFGS ? p->m : 0;
+    d.max_iter = p->max_iter;
+    d.precision = p->precision;
+    d.linesearch = p->linesearch;
+    d.ls_K = p->ls_K;
+    d.cg_restart = p->cg_restart > 0 ? p->cg_restart : 3 * L.n;
+    d.certify = (p->flags & FF_MIN_NO_CERTIFY) ? 0 : 1;
+    d.tol = p->tol;
+    d.h_init = p->h_init;
+    d.k_plus = p->k_plus;
+    d.k_minus = p->k_minus;
+    d.eps_h = p->eps_h;
+    double* x0 = at<double>(c->ws, L.off_vec) + (size_t)V_X0 * L.vstride;
+    if (!resume) HIP_TRY(hipMemcpyAsync(x0, xyz, 3 * (size_t)L.n * 8, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_kick(a, d, resume ? 1 : 0, trace_buffer(c), kTraceCap, st));
+    if (!c->graph) {
+        ff_status gs = build_graph(c);
+        if (gs) return gs;
+    }
+    c->last_method = p->method;
+    c->last_m = p->m;
+    c->last_prec = p->precision;
+    // poll (phase, done, term, iters, evals): contiguous in the control block
+    const char* dev_state = c->ws + L.off_ctl + offsetof(Ctl, phase);
+    int32_t* hs = c->host_flag;
+    int batch = 4;
+    int last_evals = -1;
+    for (;;) {
+        for (int k = 0; k < batch; ++k) HIP_TRY(hipGraphLaunch(c->graph, st));
+        HIP_TRY(hipMemcpyAsync(hs, dev_state, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hs[1]) break;
+        // every cycle that is not an accept pass evaluates; a batch without a
+        // new evaluation means the decision logic has stopped requesting work
+        if (hs[4] == last_evals) return fail(FF_ERR_HIP, "minimizer stalled in phase %d", hs[0]);
+        last_evals = hs[4];
+        batch = std::min(batch * 2, 64);
+    }
+    HIP_TRY(hipMemcpyAsync(c->host_ctl, c->ws + L.off_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const Ctl& h = *c->host_ctl;
+    const int slot = h.result_slot;
+    double* xr = at<double>(c->ws, L.off_vec) + (size_t)(V_X0 + slot) * L.vstride;
+    HIP_TRY(hipMemcpyAsync(xyz, xr, 3 * (size_t)L.n * 8, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    res->term = h.term;
+    res->iters = h.iters - h.iters_base;
+    res->evals = h.evals;
+    res->evals_fp64 = h.evals64;
+    res->energy = h.e[slot];
+    res->grad_inf = h.ginf[slot];
+    res->grad_2 = std::sqrt(h.g2[slot]);
+    return FF_OK;
+}
+
+// Per-iteration trace of the last ff_minimize call: out[3k..3k+2] = (E after
+// iteration k, accepted step h, evaluations so far).  Returns the number of
+// entries written (at most max_entries), or a negative ff_status.
+int32_t ff_get_trace(ff_ctx* c, double* host_out, int32_t max_entries, void* stream) {
+    if (!c || !host_out || max_entries < 0) return fail(FF_ERR_ARG, "bad arguments");
+    stream = stream ? stream : (void*)c->own;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t n = 0;
+    if (hipMemcpyAsync(&n, c->ws + c->L.off_ctl + offsetof(Ctl, n_trace), 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(FF_ERR_HIP, "trace count copy failed");
+    n = std::min(n, max_entries);
+    if (n > 0 && (hipMemcpyAsync(host_out, trace_buffer(c), 3 * (size_t)n * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                  hipStreamSynchronize(st) != hipSuccess))
+        return fail(FF_ERR_HIP, "trace copy failed");
+    return n;
+}
+
+}  // extern "C"

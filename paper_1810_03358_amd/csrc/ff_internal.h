@@ -1,0 +1,182 @@
+// Internal layout shared by the kernels and the host side of libff_mi355x.
+//
+// Workspace (caller-allocated device memory) =
+//   [control block | packed parameters | topology | tile tables |
+//    pair partials | bonded partials | reduction partials | FP64 vectors]
+// Every region starts on a 256-byte boundary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ff {
+
+constexpr int kAtomAlign = 512;      // padded atom count is a multiple of this
+constexpr int kTile = 64;            // j-tile: one atom per lane of a wavefront
+constexpr int kExclWindow = 64;      // exclusions reach at most 64 atoms ahead
+constexpr int kMaxM = 32;            // largest L-BFGS memory
+constexpr int kNumSlots = 8;         // point slots (x and grad) of the optimizer
+constexpr int kMaxTerms = 2 * kMaxM + 2;   // linear-combination terms of a direction
+constexpr int kGramDim = 2 * kMaxM + 1;    // Gram matrix over {s_i, y_i, g}
+constexpr int kFinBlock = 256;       // threads of the finalize / vector kernels
+constexpr int kMaxDots = 6 * kMaxM + 8;    // dot products per vector pass
+constexpr int kMaxLsTrials = 8;
+constexpr int kBondedPerBlock = 256;  // bonded terms per workgroup
+constexpr int kTraceCap = 4096;       // per-iteration trace entries kept
+
+// Distances (A^2) below which the FP32 pair path first corrects the
+// displacement with the low halves of the double-single coordinates and,
+// below the second one, evaluates the pair entirely in FP64 (clashes).
+constexpr float kCorrR2 = 25.0f;
+constexpr double kClashR2 = 4.0;
+
+// ---------------------------------------------------------------- vector ids
+// All FP64 optimizer vectors have 3*np doubles and are laid out back to back
+// with stride vstride; a vector is named by its index.
+enum VecId : int32_t {
+    V_X0 = 0,                          // point slots x[0..kNumSlots)
+    V_G0 = V_X0 + kNumSlots,           // gradient slots g[0..kNumSlots)
+    V_D = V_G0 + kNumSlots,            // current unit direction
+    V_R,                               // CG running (unnormalized) direction
+    V_S0,                              // L-BFGS s vectors (kMaxM + 1 incl. spare)
+    V_Y0 = V_S0 + kMaxM + 1,           // L-BFGS y vectors
+    V_COUNT = V_Y0 + kMaxM + 1
+};
+
+// ------------------------------------------------------------ control block
+enum Action : int32_t { ACT_NONE = 0, ACT_EVAL = 1 };
+enum PointMode : int32_t {
+    PM_USE = 0,        // evaluate x[target] as it is
+    PM_TRIAL = 1,      // x[target] = x[base] + h * d
+    PM_DIR_TRIAL = 2,  // d = sum_k coef_k v_k (optionally also r), then as PM_TRIAL
+    PM_MOMENTUM = 3    // x[target] = x[base] + beta * (x[base] - x[prev])
+};
+enum Phase : int32_t {
+    PH_IDLE = 0, PH_START, PH_LS, PH_MOMENTUM, PH_REEVAL64, PH_CERTIFY, PH_DONE
+};
+enum LsKind : int32_t { LSK_PAR = 0, LSK_H = 1 };
+enum LsHStage : int32_t { LSH_F0 = 0, LSH_F1 = 1, LSH_SHRINK = 2 };
+
+struct MinParamsDev {
+    int32_t method, m, max_iter, precision, linesearch, ls_K, cg_restart, certify;
+    double tol, h_init, k_plus, k_minus, eps_h;
+};
+
+struct Ctl {
+    // ---- request for the next evaluation cycle (written by the decision step)
+    int32_t action;
+    int32_t point_mode;
+    int32_t prec;            // ff_precision of this evaluation
+    int32_t target;          // slot evaluated
+    int32_t base;            // trial base slot
+    int32_t prev;            // momentum: previous point slot
+    int32_t want_slope;      // finalize also computes <g[base], d>
+    int32_t write_r;         // PM_DIR_TRIAL: also store the unnormalized r
+    double h;                // trial step
+    double beta;             // momentum coefficient
+    int32_t n_terms;
+    int32_t term_vec[kMaxTerms];
+    double term_coef[kMaxTerms];   // coefficients of r (unnormalized)
+    double dir_scale;              // |r|: d = r / dir_scale
+
+    // ---- accept request for the vector pass after a successful line search
+    int32_t accept;          // 1: k_accept has work this cycle
+    int32_t acc_new, acc_old;
+    int32_t n_dots;
+    int32_t dot_a[kMaxDots], dot_b[kMaxDots];
+    double dot_val[kMaxDots];
+
+    // ---- per-slot results
+    double e[kNumSlots], ginf[kNumSlots], g2[kNumSlots];
+    int32_t slot_prec[kNumSlots];
+    double slope;            // <g[base], d> of the current line search
+
+    // ---- optimizer state
+    MinParamsDev p;
+    int32_t phase, done, term, iters, evals, evals64, iters_limit, iters_base;
+    int32_t cur, prev_x, best, w;          // slots
+    int32_t prec_now;                      // precision of the running phase
+    int32_t escalated;
+    double h_prev;
+    // line search
+    int32_t ls_kind, ls_hstage, ls_base, ls_best, ls_ntrials, ls_primary, ls_fallback_done;
+    double ls_fstar, ls_s0, ls_hcur, ls_hmin, ls_h0;
+    double ls_th[kMaxLsTrials + 1], ls_tf[kMaxLsTrials + 1];
+    // method state
+    int32_t steepest;        // the current direction is -g
+    double theta_prev, fgm_theta, fgm_beta;  // FGM
+    double accept_h;                         // step of the last accepted trial
+    double cg_beta, r_norm2, r_dot_g_old, g_dot_g_old;   // CG
+    int32_t hist_n, hist_head;               // L-BFGS ring: positions 0..hist_n-1 oldest..newest
+    int32_t hist_s[kMaxM + 1], hist_y[kMaxM + 1];   // vector ids by ring position
+    int32_t spare_s, spare_y;                        // vector ids for the next pair
+    int32_t spare_s_next, spare_y_next;              // first never-used ids
+    double rho[kMaxM];
+    double gram[kGramDim * kGramDim];        // over positions [s_0..s_{n-1}, y_0..y_{n-1}, g]
+    int32_t result_slot;
+    // per-iteration trace (E, accepted h, evaluations so far)
+    double* trace_ptr;
+    int32_t trace_cap, n_trace;
+
+    // ---- reduction tickets (last-block-done pattern)
+    uint32_t ticket_fin, ticket_acc, ticket_prep;
+};
+
+// ------------------------------------------------------------- tile tables
+struct ChunkInfo {        // one workgroup of the pair kernel
+    int32_t row;          // I-block index
+    int32_t t_begin, t_end;   // j-tiles [t_begin, t_end)
+    int32_t unit_base;    // index of unit (row, t_begin) in the Fj partial array
+};
+struct RowInfo {          // one I-block
+    int32_t unit_start;   // unit index of (row, t0)
+    int32_t t0;           // first j-tile (diagonal)
+    int32_t chunk_start;
+    int32_t n_chunks;
+};
+
+struct Layout {
+    int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;
+    int32_t n_bonds, n_angles, n_dihedrals, n_terms_slots, n_bonded_blocks;
+    int32_t n_fin_blocks;
+    int32_t m_max;
+    int32_t cfg;              // tile configuration index
+    size_t vstride;           // doubles between vectors
+    // byte offsets
+    size_t off_ctl, off_c12, off_c6, off_q, off_c12d, off_c6d, off_qd, off_excl;
+    size_t off_chunks, off_rows, off_pi, off_pj, off_ep;
+    size_t off_bond, off_bondp, off_angle, off_anglep, off_dih, off_dihp;
+    size_t off_fb, off_eb, off_inc_start, off_inc;
+    size_t off_red, off_vec;
+    size_t total;
+};
+
+// Kernel arguments: everything is derived from the workspace base and the
+// layout, plus the direct-mode pointers of ff_energy_grad.
+struct Args {
+    Layout L;
+    char* ws;
+    const double* xyz_in;    // direct mode: coordinates
+    double* e_out;           // direct mode: energy
+    double* g_out;           // direct mode: gradient or null
+    int32_t direct;          // 1: ff_energy_grad, 0: optimizer cycle
+    int32_t direct_prec;
+};
+
+template <typename T>
+__host__ __device__ inline T* at(char* ws, size_t off) { return reinterpret_cast<T*>(ws + off); }
+
+__host__ __device__ inline double* vec(const Args& a, int32_t id) {
+    return at<double>(a.ws, a.L.off_vec) + (size_t)id * a.L.vstride;
+}
+
+// Coordinates of padding atoms (index >= n): far away, mutually separated,
+// with zero parameters, so every pair they are in contributes exactly zero.
+__host__ __device__ inline void pad_position(int32_t a, int32_t n, double* p) {
+    p[0] = 1.0e6 + 16.0 * (double)(a - n);
+    p[1] = -1.0e6;
+    p[2] = 1.0e6;
+}
+
+}  // namespace ff

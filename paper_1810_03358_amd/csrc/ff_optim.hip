@@ -1,0 +1,340 @@
+// Per-evaluation finalize (gradient gather, norms, energy total) and the
+// optimizer's vector passes: trial point / direction construction and the
+// accept pass (history vectors and their dot products).  Each kernel closes
+// with a deterministic fixed-order reduction in its last workgroup
+// (last-block-done ticket), which then runs the decision step.
+#include "ff_decide.h"
+
+namespace ff {
+
+__device__ __forceinline__ Ctl* ctl_rw(const Args& a) { return at<Ctl>(a.ws, a.L.off_ctl); }
+
+// Wavefront sum of a double (xor butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum (or max for index 0 if first_is_max) of NV per-thread values over a
+// 256-thread block; thread 0 receives the totals in out[].
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], bool first_is_max, double* out) {
+    __shared__ double s[kFinBlock / 64][NV > 0 ? NV : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double r = (k == 0 && first_is_max) ? wave_max(v[k]) : wave_sum(v[k]);
+        if (lane == 0) s[wave][k] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double r = s[0][k];
+            for (int w = 1; w < kFinBlock / 64; ++w) r = (k == 0 && first_is_max) ? fmax(r, s[w][k]) : r + s[w][k];
+            out[k] = r;
+        }
+    }
+    __syncthreads();
+}
+
+// Last-block-done: returns true in every thread of the workgroup that
+// finished last.  The ticket counter is reset by that workgroup.
+__device__ __forceinline__ bool last_block(uint32_t* ticket) {
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = atomicAdd(ticket, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) {
+        __threadfence();
+        if (threadIdx.x == 0) atomicExch(ticket, 0u);
+    }
+    return is_last != 0;
+}
+
+// Fixed-order sum of n doubles by one 256-thread block (result in thread 0).
+__device__ __forceinline__ double block_sum_array(const double* p, int n, bool is_max = false) {
+    double v = is_max ? 0.0 : 0.0;
+    for (int i = threadIdx.x; i < n; i += kFinBlock) v = is_max ? fmax(v, p[i]) : v + p[i];
+    double arr[1] = {v};
+    __shared__ double res;
+    double out[1];
+    block_reduce<1>(arr, is_max, out);
+    if (threadIdx.x == 0) res = out[0];
+    __syncthreads();
+    const double r = res;
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ finalize
+// One thread per atom: gradient = sum of the pair partials of its I-block
+// (all chunks of its row), of the j partials of every unit holding it, and
+// of its bonded-term slots.  Then |g|_inf, |g|^2, optionally <g_base, d>, and
+// E = sum of the pair-workgroup and bonded-block energies.
+__global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
+    const Layout& L = a.L;
+    Ctl* c = ctl_rw(a);
+    if (!a.direct && (c->action != ACT_EVAL || c->target < 0 || c->target >= kNumSlots)) return;
+    double* G = a.direct ? a.g_out : vec(a, V_G0 + c->target);
+    const bool want_slope = !a.direct && c->want_slope;
+    const int atom = blockIdx.x * kFinBlock + threadIdx.x;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if (atom < L.n) {
+        const int row = atom / L.block, il = atom - row * L.block;
+        const int t = atom / kTile, jl = atom - t * kTile;
+        const RowInfo* R = at<RowInfo>(a.ws, L.off_rows);
+        const double* Pi = at<double>(a.ws, L.off_pi);
+        const double* Pj = at<double>(a.ws, L.off_pj);
+        const RowInfo ri = R[row];
+        for (int ch = ri.chunk_start; ch < ri.chunk_start + ri.n_chunks; ++ch) {
+            const double* p = Pi + ((size_t)ch * L.block + il) * 3;
+            gx += p[0]; gy += p[1]; gz += p[2];
+        }
+        for (int r = 0; r <= row; ++r) {
+            const RowInfo rr = R[r];
+            const double* p = Pj + ((size_t)(rr.unit_start + t - rr.t0) * kTile + jl) * 3;
+            gx += p[0]; gy += p[1]; gz += p[2];
+        }
+        const int* inc0 = at<int>(a.ws, L.off_inc_start);
+        const int* inc = at<int>(a.ws, L.off_inc);
+        const double* FB = at<double>(a.ws, L.off_fb);
+        for (int k = inc0[atom]; k < inc0[atom + 1]; ++k) {
+            const double* p = FB + 3 * (size_t)inc[k];
+            gx += p[0]; gy += p[1]; gz += p[2];
+        }
+        if (G) { G[3 * (size_t)atom] = gx; G[3 * (size_t)atom + 1] = gy; G[3 * (size_t)atom + 2] = gz; }
+    }
+    double v[3];
+    v[0] = fmax(fabs(gx), fmax(fabs(gy), fabs(gz)));
+    if (isnan(gx) || isnan(gy) || isnan(gz)) v[0] = __builtin_inf();
+    v[1] = gx * gx + gy * gy + gz * gz;
+    v[2] = 0.0;
+    if (want_slope && atom < L.n) {
+        const double* gb = vec(a, V_G0 + c->base);
+        const double* d = vec(a, V_D);
+        const size_t o = 3 * (size_t)atom;
+        v[2] = gb[o] * d[o] + gb[o + 1] * d[o + 1] + gb[o + 2] * d[o + 2];
+    }
+    double* red = at<double>(a.ws, L.off_red);
+    double tot[3];
+    block_reduce<3>(v, true, tot);
+    if (threadIdx.x == 0) { red[3 * blockIdx.x] = tot[0]; red[3 * blockIdx.x + 1] = tot[1]; red[3 * blockIdx.x + 2] = tot[2]; }
+    if (!last_block(&c->ticket_fin)) return;
+    // ---- last workgroup: totals in a fixed order
+    double w[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kFinBlock) {
+        w[0] = fmax(w[0], red[3 * b]);
+        w[1] += red[3 * b + 1];
+        w[2] += red[3 * b + 2];
+    }
+    double gt[3];
+    block_reduce<3>(w, true, gt);
+    const double e_pair = block_sum_array(at<double>(a.ws, L.off_ep), L.n_chunks);
+    const double e_bond = block_sum_array(at<double>(a.ws, L.off_eb), L.n_bonded_blocks);
+    if (threadIdx.x != 0) return;
+    const double E = e_pair + e_bond;
+    if (a.direct) {
+        if (a.e_out) *a.e_out = E;
+        return;
+    }
+    const int t = c->target;
+    c->e[t] = E;
+    c->ginf[t] = gt[0];
+    c->g2[t] = gt[1];
+    if (want_slope) c->slope = gt[2];
+    after_eval(c);
+}
+
+// ------------------------------------------------------------------- prepare
+// Builds the point to evaluate: a trial x + h d, the direction itself
+// (d = r / |r| with r a linear combination of stored vectors) followed by the
+// trial, or the FGM momentum point.  Rounding is kept explicit (no
+// contraction) so that trial points are reproducible.
+__global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
+    const Ctl* c = ctl_rw(a);
+    if (c->action != ACT_EVAL || c->point_mode == PM_USE) return;
+    if (c->target < 0 || c->target >= kNumSlots || c->base < 0 || c->base >= kNumSlots) return;
+    if (c->point_mode == PM_MOMENTUM && (c->prev < 0 || c->prev >= kNumSlots)) return;
+    const int n3 = 3 * a.L.n;
+    const int i = blockIdx.x * kFinBlock + threadIdx.x;
+    if (i >= n3) return;
+    double* xt = vec(a, V_X0 + c->target);
+    const double* xb = vec(a, V_X0 + c->base);
+    if (c->point_mode == PM_MOMENTUM) {
+        const double* xp = vec(a, V_X0 + c->prev);
+        xt[i] = __dadd_rn(xb[i], __dmul_rn(c->beta, __dsub_rn(xb[i], xp[i])));
+        return;
+    }
+    double* d = vec(a, V_D);
+    double di;
+    if (c->point_mode == PM_DIR_TRIAL) {
+        double r = __dmul_rn(c->term_coef[0], vec(a, c->term_vec[0])[i]);
+        for (int k = 1; k < c->n_terms; ++k) r = __dadd_rn(r, __dmul_rn(c->term_coef[k], vec(a, c->term_vec[k])[i]));
+        if (c->write_r) vec(a, V_R)[i] = r;
+        di = __ddiv_rn(r, c->dir_scale);
+        d[i] = di;
+    } else {
+        di = d[i];
+    }
+    xt[i] = __dadd_rn(xb[i], __dmul_rn(c->h, di));
+}
+
+// -------------------------------------------------------------------- accept
+// After a successful line search: method-specific vectors and dot products.
+//  CG:     <g_new, g_old>, <g_new, r_old>
+//  L-BFGS: s = x_new - x_old and y = g_new - g_old into the spare history
+//          vectors, then <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for every
+//          stored pair i, <s,S_i> <s,Y_i> <y,S_i> <y,Y_i> <g,S_i> <g,Y_i>.
+__global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
+    Ctl* c = ctl_rw(a);
+    if (!c->accept) return;
+    const int n3 = 3 * a.L.n;
+    const int i = blockIdx.x * kFinBlock + threadIdx.x;
+    const bool in = i < n3;
+    const int method = c->p.method;
+    double* red = at<double>(a.ws, a.L.off_red);
+    int nd = 0;
+    if (method == M_CG) {
+        nd = 2;
+        double v[2] = {0.0, 0.0};
+        if (in) {
+            const double gn = vec(a, V_G0 + c->acc_new)[i];
+            v[0] = gn * vec(a, V_G0 + c->acc_old)[i];
+            v[1] = gn * vec(a, V_R)[i];
+        }
+        double tot[2];
+        block_reduce<2>(v, false, tot);
+        if (threadIdx.x == 0) { red[nd * blockIdx.x] = tot[0]; red[nd * blockIdx.x + 1] = tot[1]; }
+    } else if (method == M_LBFGS) {
+        const int nh = c->hist_n;
+        nd = 6 + 6 * nh;
+        double s = 0.0, y = 0.0, g = 0.0;
+        if (in) {
+            s = __dsub_rn(vec(a, V_X0 + c->acc_new)[i], vec(a, V_X0 + c->acc_old)[i]);
+            g = vec(a, V_G0 + c->acc_new)[i];
+            y = __dsub_rn(g, vec(a, V_G0 + c->acc_old)[i]);
+            vec(a, c->spare_s)[i] = s;
+            vec(a, c->spare_y)[i] = y;
+        }
+        double v6[6] = {s * y, y * y, s * s, g * s, g * y, g * g};
+        double tot[6];
+        block_reduce<6>(v6, false, tot);
+        if (threadIdx.x == 0) for (int k = 0; k < 6; ++k) red[nd * blockIdx.x + k] = tot[k];
+        for (int h = 0; h < nh; ++h) {
+            double S = 0.0, Y = 0.0;
+            if (in) { S = vec(a, c->hist_s[h])[i]; Y = vec(a, c->hist_y[h])[i]; }
+            double w6[6] = {s * S, s * Y, y * S, y * Y, g * S, g * Y};
+            block_reduce<6>(w6, false, tot);
+            if (threadIdx.x == 0) for (int k = 0; k < 6; ++k) red[nd * blockIdx.x + 6 + 6 * h + k] = tot[k];
+        }
+    }
+    if (!last_block(&c->ticket_acc)) return;
+    __shared__ double dots[kMaxDots];
+    for (int k = 0; k < nd; ++k) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += kFinBlock) acc += red[nd * b + k];
+        double arr[1] = {acc}, out[1];
+        block_reduce<1>(arr, false, out);
+        if (threadIdx.x == 0) dots[k] = out[0];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    after_accept(c, dots);
+}
+
+// ---------------------------------------------------------------------- kick
+// Starts (or resumes) a minimization: one thread sets up the control block.
+__global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int trace_cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Ctl* c = ctl_rw(a);
+    if (resume) {
+        c->p = p;
+        c->done = 0;
+        c->iters_limit = c->iters + p.max_iter;
+        c->trace_ptr = trace;
+        c->trace_cap = trace_cap;
+        c->n_trace = 0;
+        c->iters_base = c->iters;
+        begin_iteration(c);
+        return;
+    }
+    c->p = p;
+    c->phase = PH_START;
+    c->done = 0;
+    c->term = -1;
+    c->iters = 0;
+    c->iters_base = 0;
+    c->evals = 0;
+    c->evals64 = 0;
+    c->iters_limit = p.max_iter;
+    c->cur = 0;
+    c->prev_x = p.method == M_FGM ? 0 : -1;
+    c->best = -1;
+    c->w = -1;
+    c->ls_base = -1;
+    c->ls_best = -1;
+    c->prec_now = p.precision;
+    c->escalated = 0;
+    c->h_prev = p.h_init;
+    c->steepest = 1;
+    c->theta_prev = 1.0;
+    c->fgm_beta = 0.0;
+    c->cg_beta = 0.0;
+    c->accept = 0;
+    c->result_slot = 0;
+    lbfgs_clear(c);
+    for (int s = 0; s < kNumSlots; ++s) c->slot_prec[s] = -1;
+    c->trace_ptr = trace;
+    c->trace_cap = trace_cap;
+    c->n_trace = 0;
+    c->ticket_fin = c->ticket_acc = c->ticket_prep = 0u;
+    request_eval(c, PM_USE, 0, 0);
+}
+
+// Clears the tickets and marks the context idle (after ff_create).
+__global__ void k_reset_ctl(Args a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Ctl* c = ctl_rw(a);
+    c->ticket_fin = c->ticket_acc = c->ticket_prep = 0u;
+    c->action = ACT_NONE;
+    c->accept = 0;
+    c->done = 1;
+    c->phase = PH_IDLE;
+    c->iters = 0;
+}
+
+hipError_t launch_finalize(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(a.L.n_fin_blocks), dim3(kFinBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s) {
+    const int blocks = (3 * a.L.n + kFinBlock - 1) / kFinBlock;
+    if (which == 0) hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(kFinBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kFinBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick(const Args& a, const MinParamsDev& p, int resume, double* trace, int trace_cap,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_kick, dim3(1), dim3(64), 0, s, a, p, resume, trace, trace_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ff

@@ -1,0 +1,531 @@
+// Nonbonded all-pairs energy and gradient (Coulomb + 12-6 Lennard-Jones with
+// geometric mixing, section 2 of the paper) and the bonded terms (stretch,
+// bend, OPLS torsion, section 2), for one evaluation point.
+//
+// Work decomposition.  Atoms are padded to np (multiple of 512) with
+// zero-parameter atoms placed far away.  The upper triangle of the pair
+// matrix is cut into units (I-block of B atoms) x (j-tile of 64 atoms), j-tile
+// index t >= B*row/64; a workgroup ("chunk") walks a run of j-tiles of one
+// I-block.  Each lane keeps IPL i-atoms in registers; the j-tile sits in LDS
+// twice in a row so that at step s lane l reads entry l+s (atom (l+s) mod 64)
+// with an immediate offset.  The gradient on j is accumulated in a register
+// that moves one lane down after every step (DPP wave rotation), so after 64
+// steps every lane again holds the sum for "its" j.  Per-tile FP32 sums are
+// folded into FP64; per-unit j sums and per-chunk i sums are written to
+// partial buffers that the finalize kernel adds up in a fixed order, so the
+// result is deterministic.  Newton's third law is used: every pair is
+// computed once.
+//
+// Per pair, with per-atom factors prepared once per system
+//   c12 = 2 sqrt(eps) sigma^6,  c6 = 2 sqrt(eps) sigma^3,  q^ = sqrt(C) q
+// (so c12_i c12_j = 4 eps_ij sigma_ij^12, c6_i c6_j = 4 eps_ij sigma_ij^6,
+//  q^_i q^_j = C q_i q_j):
+//   e12 = c12_i c12_j / r^12, e6 = c6_i c6_j / r^6, ec = q^_i q^_j / r
+//   E  += e12 - e6 + ec
+//   f   = (12 e12 - 6 e6 + ec) / r^2,  d = x_j - x_i
+//   grad_i += f d,  grad_j -= f d
+#include "ff_internal.h"
+
+namespace ff {
+
+#ifndef FF_DPP_ROTATE
+#define FF_DPP_ROTATE 0x134   // wave_rol:1 -- lane l receives lane (l+1) mod 64
+#endif
+
+__device__ __forceinline__ float rotate_down(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), FF_DPP_ROTATE, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double rotate_down(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), FF_DPP_ROTATE, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), FF_DPP_ROTATE, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ const Ctl* ctl_of(const Args& a) { return at<Ctl>(a.ws, a.L.off_ctl); }
+
+__device__ __forceinline__ bool eval_active(const Args& a, int prec) {
+    if (a.direct) return a.direct_prec == prec;
+    const Ctl* c = ctl_of(a);
+    return c->action == ACT_EVAL && c->prec == prec && c->target >= 0 && c->target < kNumSlots;
+}
+
+__device__ __forceinline__ const double* eval_coords(const Args& a) {
+    if (a.direct) return a.xyz_in;
+    return vec(a, V_X0 + ctl_of(a)->target);
+}
+
+__device__ __forceinline__ void load_pos(const double* X, int32_t atom, int32_t n, double* p) {
+    if (atom < n) {
+        p[0] = X[3 * (size_t)atom];
+        p[1] = X[3 * (size_t)atom + 1];
+        p[2] = X[3 * (size_t)atom + 2];
+    } else {
+        pad_position(atom, n, p);
+    }
+}
+
+// ------------------------------------------------------------------ bonded
+// One thread per bond, angle or dihedral; FP64.  The gradient of each term
+// on each of its atoms goes to its own slot (no scatter), the energy to a
+// per-block partial.
+// Energy of bonded term t (bonds, then angles, then dihedrals) and its
+// gradient on each of its atoms, written to the term's own slots.
+__device__ double bonded_term(const Args& a, const double* X, int t) {
+    const Layout& L = a.L;
+    double e = 0.0;
+    double* FB = at<double>(a.ws, L.off_fb);
+    if (t < L.n_bonds) {
+        const int2 b = at<int2>(a.ws, L.off_bond)[t];
+        const double2 kp = at<double2>(a.ws, L.off_bondp)[t];   // (K, r0)
+        double d[3], r2 = 0.0;
+        for (int c = 0; c < 3; ++c) { d[c] = X[3 * b.x + c] - X[3 * b.y + c]; r2 += d[c] * d[c]; }
+        const double r = sqrt(r2);
+        const double dr = r - kp.y;
+        e = kp.x * dr * dr;
+        const double s = 2.0 * kp.x * dr / r;
+        double* o = FB + 6 * (size_t)t;
+        for (int c = 0; c < 3; ++c) { o[c] = s * d[c]; o[3 + c] = -s * d[c]; }
+    } else if (t < L.n_bonds + L.n_angles) {
+        const int k = t - L.n_bonds;
+        const int* ia = at<int>(a.ws, L.off_angle) + 3 * k;
+        const double2 kp = at<double2>(a.ws, L.off_anglep)[k];  // (K, theta0)
+        double u[3], v[3];
+        for (int c = 0; c < 3; ++c) {
+            u[c] = X[3 * ia[0] + c] - X[3 * ia[1] + c];
+            v[c] = X[3 * ia[2] + c] - X[3 * ia[1] + c];
+        }
+        // w = u x v; theta = atan2(|w|, u.v);
+        // d theta/d x_i = (u x w)/(|u|^2 |w|), d theta/d x_k = -(v x w)/(|v|^2 |w|)
+        const double w[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        const double nw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+        const double th = atan2(nw, uv);
+        const double dth = th - kp.y;
+        e = kp.x * dth * dth;
+        const double de = 2.0 * kp.x * dth;
+        const double uxw[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        const double vxw[3] = {v[1] * w[2] - v[2] * w[1], v[2] * w[0] - v[0] * w[2], v[0] * w[1] - v[1] * w[0]};
+        const double si = de / (uu * nw), sk = -de / (vv * nw);
+        double* o = FB + 6 * (size_t)L.n_bonds + 9 * (size_t)k;
+        for (int c = 0; c < 3; ++c) {
+            const double gi = si * uxw[c], gk = sk * vxw[c];
+            o[c] = gi;
+            o[3 + c] = -(gi + gk);
+            o[6 + c] = gk;
+        }
+    } else if (t < L.n_bonds + L.n_angles + L.n_dihedrals) {
+        const int k = t - L.n_bonds - L.n_angles;
+        const int* id = at<int>(a.ws, L.off_dih) + 4 * k;
+        const double* V = at<double>(a.ws, L.off_dihp) + 4 * k;
+        // F = x_a - x_b, G = x_b - x_c, H = x_d - x_c (Blondel and Karplus 1996)
+        double F[3], G[3], H[3];
+        for (int c = 0; c < 3; ++c) {
+            F[c] = X[3 * id[0] + c] - X[3 * id[1] + c];
+            G[c] = X[3 * id[1] + c] - X[3 * id[2] + c];
+            H[c] = X[3 * id[3] + c] - X[3 * id[2] + c];
+        }
+        const double A[3] = {F[1] * G[2] - F[2] * G[1], F[2] * G[0] - F[0] * G[2], F[0] * G[1] - F[1] * G[0]};
+        const double Bv[3] = {H[1] * G[2] - H[2] * G[1], H[2] * G[0] - H[0] * G[2], H[0] * G[1] - H[1] * G[0]};
+        const double AA = A[0] * A[0] + A[1] * A[1] + A[2] * A[2];
+        const double BB = Bv[0] * Bv[0] + Bv[1] * Bv[1] + Bv[2] * Bv[2];
+        const double GG = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+        const double nG = sqrt(GG);
+        // cos phi = A.B/(|A||B|); sin phi from (B x A).G/|G| (cis = 0)
+        const double AxB_G = (Bv[1] * A[2] - Bv[2] * A[1]) * G[0] + (Bv[2] * A[0] - Bv[0] * A[2]) * G[1] +
+                             (Bv[0] * A[1] - Bv[1] * A[0]) * G[2];
+        const double phi = atan2(AxB_G / nG, A[0] * Bv[0] + A[1] * Bv[1] + A[2] * Bv[2]);
+        double s1, c1, s2, c2, s3, c3, s4, c4;
+        sincos(phi, &s1, &c1);
+        sincos(2.0 * phi, &s2, &c2);
+        sincos(3.0 * phi, &s3, &c3);
+        sincos(4.0 * phi, &s4, &c4);
+        e = 0.5 * (V[0] * (1.0 + c1) + V[1] * (1.0 - c2) + V[2] * (1.0 + c3) + V[3] * (1.0 - c4));
+        const double de = 0.5 * (-V[0] * s1 + 2.0 * V[1] * s2 - 3.0 * V[2] * s3 + 4.0 * V[3] * s4);
+        const double FG = F[0] * G[0] + F[1] * G[1] + F[2] * G[2];
+        const double HG = H[0] * G[0] + H[1] * G[1] + H[2] * G[2];
+        double* o = FB + 6 * (size_t)L.n_bonds + 9 * (size_t)L.n_angles + 12 * (size_t)k;
+        for (int c = 0; c < 3; ++c) {
+            const double ga = -nG / AA * A[c];
+            const double gd = nG / BB * Bv[c];
+            const double gb = nG / AA * A[c] + FG / (AA * nG) * A[c] - HG / (BB * nG) * Bv[c];
+            const double gc = HG / (BB * nG) * Bv[c] - FG / (AA * nG) * A[c] - nG / BB * Bv[c];
+            o[c] = de * ga;
+            o[3 + c] = de * gb;
+            o[6 + c] = de * gc;
+            o[9 + c] = de * gd;
+        }
+    }
+    return e;
+}
+
+__device__ double bonded_term(const Args& a, const double* X, int t);
+
+__device__ void bonded_block(const Args& a, const double* X, int blk, int nthreads) {
+    double e = 0.0;
+    const int first = blk * kBondedPerBlock;
+    for (int t = first + (int)threadIdx.x; t < first + kBondedPerBlock; t += nthreads) e += bonded_term(a, X, t);
+    // deterministic block sum of the term energies
+    __shared__ double red[kBondedPerBlock];
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = nthreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) at<double>(a.ws, a.L.off_eb)[blk] = red[0];
+}
+
+// Bonded terms of one evaluation (any precision mode: always FP64).
+__global__ void __launch_bounds__(kBondedPerBlock) k_bonded(Args a) {
+    if (!(eval_active(a, 0) || eval_active(a, 1))) return;
+    bonded_block(a, eval_coords(a), blockIdx.x, kBondedPerBlock);
+}
+
+// ---------------------------------------------------------------- FP32 pairs
+
+template <int IPL>
+struct IAtoms32 {
+    float xh[IPL], yh[IPL], zh[IPL];     // high halves
+    float xl[IPL], yl[IPL], zl[IPL];     // low halves
+    float c12[IPL], c6[IPL], q[IPL];
+    uint64_t excl[IPL];
+    int32_t idx[IPL];
+};
+
+// A pair closer than sqrt(kCorrR2) by the high halves: redo the displacement
+// with both halves in FP64.  Below sqrt(kClashR2) the whole pair is evaluated
+// in FP64 (clash energies reach 1e15 kcal/mol at the start of a minimization)
+// and the FP32 path is switched off for it by r2 = inf.
+template <int IPL>
+__device__ __forceinline__ void close_pair32(const IAtoms32<IPL>& I, int k, float4 pj, float4 lo, float2 cj,
+                                          float& dx, float& dy, float& dz, float& r2,
+                                          double& gx, double& gy, double& gz, double& e64,
+                                          float& fjx, float& fjy, float& fjz) {
+    const double ddx = ((double)pj.x - (double)I.xh[k]) + ((double)lo.x - (double)I.xl[k]);
+    const double ddy = ((double)pj.y - (double)I.yh[k]) + ((double)lo.y - (double)I.yl[k]);
+    const double ddz = ((double)pj.z - (double)I.zh[k]) + ((double)lo.z - (double)I.zl[k]);
+    const double rr = ddx * ddx + ddy * ddy + ddz * ddz;
+    if (rr < kClashR2) {
+        const double rinv = 1.0 / sqrt(rr);
+        const double rinv2 = rinv * rinv;
+        const double rinv6 = rinv2 * rinv2 * rinv2;
+        const double e12 = (double)I.c12[k] * (double)cj.x * rinv6 * rinv6;
+        const double e6 = (double)I.c6[k] * (double)cj.y * rinv6;
+        const double ec = (double)I.q[k] * (double)pj.w * rinv;
+        e64 += (e12 - e6) + ec;
+        const double f = (12.0 * e12 - 6.0 * e6 + ec) * rinv2;
+        gx += f * ddx; gy += f * ddy; gz += f * ddz;
+        fjx -= (float)(f * ddx); fjy -= (float)(f * ddy); fjz -= (float)(f * ddz);
+        r2 = __builtin_inff();
+    } else {
+        dx = (float)ddx; dy = (float)ddy; dz = (float)ddz;
+        r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+    }
+}
+
+template <int IPL, bool MASKED>
+__device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const float2* __restrict__ s_c,
+                                       const float4* __restrict__ s_lo, int lane, int J0,
+                                       const IAtoms32<IPL>& I, float (&fx)[IPL], float (&fy)[IPL],
+                                       float (&fz)[IPL], double (&gx)[IPL], double (&gy)[IPL],
+                                       double (&gz)[IPL], float& fjx, float& fjy, float& fjz,
+                                       float& e32, double& e64) {
+#pragma unroll 4
+    for (int s = 0; s < kTile; ++s) {
+        const int js = lane + s;
+        const float4 pj = s_xq[js];
+        const float2 cj = s_c[js];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            float dx = pj.x - I.xh[k];
+            float dy = pj.y - I.yh[k];
+            float dz = pj.z - I.zh[k];
+            float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            if (MASKED) {
+                const int delta = J0 + (js & (kTile - 1)) - I.idx[k];
+                const unsigned dm1 = (unsigned)(delta - 1);
+                const bool excl = dm1 < (unsigned)kExclWindow && ((I.excl[k] >> (dm1 & 63u)) & 1ull);
+                r2 = (delta > 0 && !excl) ? r2 : __builtin_inff();
+            }
+            if (r2 < kCorrR2)
+                close_pair32<IPL>(I, k, pj, s_lo[js], cj, dx, dy, dz, r2, gx[k], gy[k], gz[k], e64, fjx, fjy, fjz);
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float rinv2 = rinv * rinv;
+            const float rinv6 = rinv2 * rinv2 * rinv2;
+            const float e6 = I.c6[k] * cj.y * rinv6;
+            const float e12 = I.c12[k] * cj.x * rinv6 * rinv6;
+            const float ec = I.q[k] * pj.w * rinv;
+            const float lj = e12 - e6;
+            e32 += lj + ec;
+            const float f = __fmaf_rn(6.0f, lj + e12, ec) * rinv2;     // 12 e12 - 6 e6 + ec
+            fx[k] = __fmaf_rn(f, dx, fx[k]);
+            fy[k] = __fmaf_rn(f, dy, fy[k]);
+            fz[k] = __fmaf_rn(f, dz, fz[k]);
+            fjx = __fmaf_rn(-f, dx, fjx);
+            fjy = __fmaf_rn(-f, dy, fjy);
+            fjz = __fmaf_rn(-f, dz, fjz);
+        }
+        fjx = rotate_down(fjx);
+        fjy = rotate_down(fjy);
+        fjz = rotate_down(fjz);
+    }
+}
+
+__device__ __forceinline__ void split(double v, float& hi, float& lo) {
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+template <int WAVES>
+__device__ __forceinline__ void block_energy_store(double e, double* out) {
+    __shared__ double red[64 * WAVES];
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int s = 32 * WAVES; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+template <int WAVES, int IPL>
+__global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
+    if (!eval_active(a, 1)) return;
+    const double* X = eval_coords(a);
+    const Layout& L = a.L;
+    const int wg = blockIdx.x;
+    constexpr int B = 64 * WAVES * IPL;
+    const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = L.n;
+    const float* C12 = at<float>(a.ws, L.off_c12);
+    const float* C6 = at<float>(a.ws, L.off_c6);
+    const float* Q = at<float>(a.ws, L.off_q);
+    const uint64_t* EX = at<uint64_t>(a.ws, L.off_excl);
+    const int I0 = ch.row * B;
+
+    IAtoms32<IPL> I;
+    double gx[IPL], gy[IPL], gz[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = I0 + wave * 64 * IPL + k * 64 + lane;
+        double p[3];
+        load_pos(X, i, n, p);
+        split(p[0], I.xh[k], I.xl[k]);
+        split(p[1], I.yh[k], I.yl[k]);
+        split(p[2], I.zh[k], I.zl[k]);
+        I.c12[k] = C12[i]; I.c6[k] = C6[i]; I.q[k] = Q[i];
+        I.excl[k] = EX[i];
+        I.idx[k] = i;
+        gx[k] = gy[k] = gz[k] = 0.0;
+    }
+    __shared__ float4 s_xq[2 * kTile];
+    __shared__ float2 s_c[2 * kTile];
+    __shared__ float4 s_lo[2 * kTile];
+    __shared__ float s_fj[WAVES][3][kTile];
+    double e64 = 0.0;
+    const int t_masked_end = (I0 + B) / kTile + 1;   // tiles that can hold j <= i or exclusions
+    for (int t = ch.t_begin; t < ch.t_end; ++t) {
+        const int J0 = t * kTile;
+        __syncthreads();
+        if (threadIdx.x < kTile) {
+            const int j = J0 + threadIdx.x;
+            double p[3];
+            load_pos(X, j, n, p);
+            float4 h, l;
+            split(p[0], h.x, l.x);
+            split(p[1], h.y, l.y);
+            split(p[2], h.z, l.z);
+            h.w = Q[j];
+            l.w = 0.0f;
+            const float2 c = make_float2(C12[j], C6[j]);
+            s_xq[threadIdx.x] = h; s_xq[threadIdx.x + kTile] = h;
+            s_lo[threadIdx.x] = l; s_lo[threadIdx.x + kTile] = l;
+            s_c[threadIdx.x] = c;  s_c[threadIdx.x + kTile] = c;
+        }
+        __syncthreads();
+        float fx[IPL], fy[IPL], fz[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
+        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, e32 = 0.0f;
+        if (t < t_masked_end)
+            tile32<IPL, true>(s_xq, s_c, s_lo, lane, J0, I, fx, fy, fz, gx, gy, gz, fjx, fjy, fjz, e32, e64);
+        else
+            tile32<IPL, false>(s_xq, s_c, s_lo, lane, J0, I, fx, fy, fz, gx, gy, gz, fjx, fjy, fjz, e32, e64);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) { gx[k] += fx[k]; gy[k] += fy[k]; gz[k] += fz[k]; }
+        e64 += e32;
+        s_fj[wave][0][lane] = fjx;
+        s_fj[wave][1][lane] = fjy;
+        s_fj[wave][2][lane] = fjz;
+        __syncthreads();
+        if (wave == 0) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                sx += (double)s_fj[w][0][lane];
+                sy += (double)s_fj[w][1][lane];
+                sz += (double)s_fj[w][2][lane];
+            }
+            double* pj = at<double>(a.ws, L.off_pj) + ((size_t)(ch.unit_base + t - ch.t_begin) * kTile + lane) * 3;
+            pj[0] = sx; pj[1] = sy; pj[2] = sz;
+        }
+    }
+    double* pi = at<double>(a.ws, L.off_pi) + (size_t)wg * B * 3;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int il = wave * 64 * IPL + k * 64 + lane;
+        pi[3 * il] = gx[k]; pi[3 * il + 1] = gy[k]; pi[3 * il + 2] = gz[k];
+    }
+    block_energy_store<WAVES>(e64, at<double>(a.ws, L.off_ep) + wg);
+}
+
+// ---------------------------------------------------------------- FP64 pairs
+
+template <int IPL, bool MASKED>
+__device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const double2* __restrict__ s_c,
+                                       int lane, int J0, const double (&xi)[IPL], const double (&yi)[IPL],
+                                       const double (&zi)[IPL], const double (&c12i)[IPL],
+                                       const double (&c6i)[IPL], const double (&qi)[IPL],
+                                       const uint64_t (&excl)[IPL], const int (&idx)[IPL],
+                                       double (&gx)[IPL], double (&gy)[IPL], double (&gz)[IPL],
+                                       double& fjx, double& fjy, double& fjz, double& e) {
+#pragma unroll 2
+    for (int s = 0; s < kTile; ++s) {
+        const int js = lane + s;
+        const double4 pj = s_xq[js];
+        const double2 cj = s_c[js];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            const double dx = pj.x - xi[k], dy = pj.y - yi[k], dz = pj.z - zi[k];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (MASKED) {
+                const int delta = J0 + (js & (kTile - 1)) - idx[k];
+                const unsigned dm1 = (unsigned)(delta - 1);
+                const bool ex = dm1 < (unsigned)kExclWindow && ((excl[k] >> (dm1 & 63u)) & 1ull);
+                r2 = (delta > 0 && !ex) ? r2 : __builtin_inf();
+            }
+            const double rinv = rsqrt(r2);
+            const double rinv2 = rinv * rinv;
+            const double rinv6 = rinv2 * rinv2 * rinv2;
+            const double e6 = c6i[k] * cj.y * rinv6;
+            const double e12 = c12i[k] * cj.x * rinv6 * rinv6;
+            const double ec = qi[k] * pj.w * rinv;
+            const double lj = e12 - e6;
+            e += lj + ec;
+            const double f = (6.0 * (lj + e12) + ec) * rinv2;
+            gx[k] += f * dx; gy[k] += f * dy; gz[k] += f * dz;
+            fjx -= f * dx; fjy -= f * dy; fjz -= f * dz;
+        }
+        fjx = rotate_down(fjx);
+        fjy = rotate_down(fjy);
+        fjz = rotate_down(fjz);
+    }
+}
+
+template <int WAVES, int IPL>
+__global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
+    if (!eval_active(a, 0)) return;
+    const double* X = eval_coords(a);
+    const Layout& L = a.L;
+    const int wg = blockIdx.x;
+    constexpr int B = 64 * WAVES * IPL;
+    const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = L.n;
+    const double* C12 = at<double>(a.ws, L.off_c12d);
+    const double* C6 = at<double>(a.ws, L.off_c6d);
+    const double* Q = at<double>(a.ws, L.off_qd);
+    const uint64_t* EX = at<uint64_t>(a.ws, L.off_excl);
+    const int I0 = ch.row * B;
+
+    double xi[IPL], yi[IPL], zi[IPL], c12i[IPL], c6i[IPL], qi[IPL], gx[IPL], gy[IPL], gz[IPL];
+    uint64_t excl[IPL];
+    int idx[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int i = I0 + wave * 64 * IPL + k * 64 + lane;
+        double p[3];
+        load_pos(X, i, n, p);
+        xi[k] = p[0]; yi[k] = p[1]; zi[k] = p[2];
+        c12i[k] = C12[i]; c6i[k] = C6[i]; qi[k] = Q[i];
+        excl[k] = EX[i];
+        idx[k] = i;
+        gx[k] = gy[k] = gz[k] = 0.0;
+    }
+    __shared__ double4 s_xq[2 * kTile];
+    __shared__ double2 s_c[2 * kTile];
+    __shared__ double s_fj[WAVES][3][kTile];
+    double e = 0.0;
+    const int t_masked_end = (I0 + B) / kTile + 1;
+    for (int t = ch.t_begin; t < ch.t_end; ++t) {
+        const int J0 = t * kTile;
+        __syncthreads();
+        if (threadIdx.x < kTile) {
+            const int j = J0 + threadIdx.x;
+            double p[3];
+            load_pos(X, j, n, p);
+            const double4 h = make_double4(p[0], p[1], p[2], Q[j]);
+            const double2 c = make_double2(C12[j], C6[j]);
+            s_xq[threadIdx.x] = h; s_xq[threadIdx.x + kTile] = h;
+            s_c[threadIdx.x] = c;  s_c[threadIdx.x + kTile] = c;
+        }
+        __syncthreads();
+        double fjx = 0.0, fjy = 0.0, fjz = 0.0;
+        if (t < t_masked_end)
+            tile64<IPL, true>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, idx, gx, gy, gz, fjx, fjy, fjz, e);
+        else
+            tile64<IPL, false>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, idx, gx, gy, gz, fjx, fjy, fjz, e);
+        s_fj[wave][0][lane] = fjx;
+        s_fj[wave][1][lane] = fjy;
+        s_fj[wave][2][lane] = fjz;
+        __syncthreads();
+        if (wave == 0) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) { sx += s_fj[w][0][lane]; sy += s_fj[w][1][lane]; sz += s_fj[w][2][lane]; }
+            double* pj = at<double>(a.ws, L.off_pj) + ((size_t)(ch.unit_base + t - ch.t_begin) * kTile + lane) * 3;
+            pj[0] = sx; pj[1] = sy; pj[2] = sz;
+        }
+    }
+    double* pi = at<double>(a.ws, L.off_pi) + (size_t)wg * B * 3;
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const int il = wave * 64 * IPL + k * 64 + lane;
+        pi[3 * il] = gx[k]; pi[3 * il + 1] = gy[k]; pi[3 * il + 2] = gz[k];
+    }
+    block_energy_store<WAVES>(e, at<double>(a.ws, L.off_ep) + wg);
+}
+
+// ------------------------------------------------------------- host launch
+// Tile configurations (index = Layout::cfg): I-block of B = 64 * waves * ipl
+// atoms.  Both precisions use the same B so that they share one chunk table.
+hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
+    const int grid = a.L.n_chunks;
+    switch (a.L.cfg) {
+    case 0:   // B = 64
+        if (prec) hipLaunchKernelGGL((k_pair32<1, 1>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_pair64<1, 1>), dim3(grid), dim3(64), 0, s, a);
+        break;
+    case 1:   // B = 256
+        if (prec) hipLaunchKernelGGL((k_pair32<4, 1>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_pair64<4, 1>), dim3(grid), dim3(256), 0, s, a);
+        break;
+    default:  // B = 512
+        if (prec) hipLaunchKernelGGL((k_pair32<4, 2>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_pair64<8, 1>), dim3(grid), dim3(512), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bonded(const Args& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_bonded, dim3(a.L.n_bonded_blocks), dim3(kBondedPerBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+
+}  // namespace ff

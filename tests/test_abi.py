@@ -1,0 +1,98 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, sizes workspaces and rejects bad input on the host (no GPU calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1810_03358_amd as ff
+from paper_1810_03358_amd import _native as N
+from synth import chain_system
+from tests.systems import make_system
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ff.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ff_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(N.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_default_params():
+    p = N.FFMinParams()
+    N.load().ff_default_params(C.byref(p))
+    assert (p.method, p.m, p.tol, p.max_iter, p.precision, p.linesearch, p.ls_K) == (
+        ff.FF_LBFGS, 10, 1e-3, 2000, ff.FF_FP64, ff.FF_LS_DEFAULT, 2)
+    assert (p.h_init, p.k_plus, p.k_minus, p.eps_h, p.cg_restart, p.flags) == (0.1, 2.0, 0.5, 1e-10, 0, 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 512, 513, 10_000, 50_000])
+def test_workspace_bytes_grows_with_size(n):
+    s = make_system(np_zeros(n))
+    b0 = ff.workspace_bytes(s, 0)
+    assert b0 > 0 and b0 % 256 == 0
+    assert ff.workspace_bytes(s, 10) == b0      # vectors are sized for the largest memory
+
+
+def np_zeros(n):
+    import numpy as np
+    return np.zeros((n, 3))
+
+
+def test_workspace_bytes_rejects_bad_sizes():
+    s = make_system(np_zeros(4))
+    assert ff.workspace_bytes(s, 33) == 0
+    assert ff.workspace_bytes(s, -1) == 0
+
+
+def _create_status(system, m_max=10, ws_ptr=256, ws_bytes=1 << 40):
+    hs = ff.HostSystem(system)
+    ctx = C.c_void_p()
+    return N.load().ff_create(C.byref(hs.c), C.c_void_p(ws_ptr), ws_bytes, m_max, None, C.byref(ctx))
+
+
+def test_create_rejects_bad_input_before_touching_the_device():
+    good = chain_system(20, 1)
+    bad_bond = dict(good, bonds=good["bonds"].copy())
+    bad_bond["bonds"][3, 1] = 20
+    assert _create_status(bad_bond) == ff.FF_ERR_ARG
+    assert "out of range" in N.last_error()
+    far = dict(good, bonds=good["bonds"].copy())
+    far["bonds"][0] = (0, 19)
+    far_big = chain_system(100, 1)
+    far_big["bonds"] = far_big["bonds"].copy()
+    far_big["bonds"][0] = (0, 90)
+    assert _create_status(far_big) == ff.FF_ERR_UNSUPPORTED
+    neg = dict(good, sigma=-good["sigma"])
+    assert _create_status(neg) == ff.FF_ERR_ARG
+    assert _create_status(good, ws_ptr=257) == ff.FF_ERR_WORKSPACE
+    assert _create_status(good, ws_bytes=1024) == ff.FF_ERR_WORKSPACE
+    assert _create_status(good, m_max=40) == ff.FF_ERR_ARG
+    self_bond = dict(good, bonds=good["bonds"].copy())
+    self_bond["bonds"][2] = (5, 5)
+    assert _create_status(self_bond) == ff.FF_ERR_ARG
+
+
+def test_product_package_does_not_import_the_oracle():
+    import ast
+    pkg = os.path.dirname(ff.__file__)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                tree = ast.parse(open(os.path.join(root, f)).read())
+                for node in ast.walk(tree):
+                    if isinstance(node, (ast.Import, ast.ImportFrom)):
+                        names = [a.name for a in node.names] + [getattr(node, "module", "") or ""]
+                        assert not any(n.split(".")[0] == "oracle" for n in names), f

@@ -1,0 +1,207 @@
+"""GPU energy/gradient parity against the FP64 CPU oracle, through the C ABI.
+
+Gates (FP64 mode): energy relative error <= 1e-6 and gradient-norm relative
+errors <= 1e-5 as required, and in practice element-wise agreement to ~1e-12.
+FP32 mode (FP32 pair terms on double-single displacements, FP64
+accumulation): the same relative gates where the gradient is large (clash-
+dominated starts), and an FP32 rounding model elsewhere: every gradient
+component within 2^-16 * sum_j |f_ij| of its atom (a few hundred FP32 ulps of
+the absolute pair forces that feed it).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1810_03358_amd as ff
+from synth import chain_system, config_system
+from tests.systems import dihedral_points, make_system, torsion_chain
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_eval(s, x, prec, ctx=None):
+    ctx = ctx or ff.Context(s, m_max=0)
+    xt = torch.tensor(np.asarray(x).reshape(-1, 3), dtype=torch.float64, device="cuda")
+    e, g = ctx.energy_grad(xt, prec)
+    torch.cuda.synchronize()
+    return float(e.cpu()[0]), g.cpu().numpy()
+
+
+def abs_pair_force_sum(s, x):
+    """sum_j |f_ij| per atom over non-excluded pairs (test-side bound only)."""
+    x = np.asarray(x).reshape(-1, 3)
+    n = len(x)
+    d = x[None, :, :] - x[:, None, :]
+    r = np.sqrt((d * d).sum(-1)) + np.eye(n)
+    sig = np.sqrt(np.outer(s["sigma"], s["sigma"]))
+    eps = np.sqrt(np.outer(s["eps"], s["eps"]))
+    qq = s["coulomb_c"] * np.outer(s["q"], s["q"])
+    sr6 = (sig / r) ** 6
+    f = np.abs(qq / r ** 2) + 4 * eps * (12 * sr6 * sr6 + 6 * sr6) / r
+    mask = np.ones((n, n), bool)
+    np.fill_diagonal(mask, False)
+    for i, j in s["bonds"]:
+        mask[i, j] = mask[j, i] = False
+    for i, _, k in s["angles"]:
+        mask[i, k] = mask[k, i] = False
+    return (f * mask).sum(1)
+
+
+def check(s, x, prec, fp64_elem=1e-11):
+    e_ref, g_ref = oracle.energy_grad(s, np.asarray(x).reshape(-1, 3))
+    e, g = gpu_eval(s, x, prec)
+    scale = max(abs(e_ref), 1e-300)
+    assert abs(e - e_ref) <= 1e-6 * scale, (prec, e, e_ref)
+    n2, n2r = np.linalg.norm(g), np.linalg.norm(g_ref)
+    ni, nir = np.abs(g).max(), np.abs(g_ref).max()
+    if prec == "fp64":
+        assert abs(n2 - n2r) <= 1e-5 * n2r and abs(ni - nir) <= 1e-5 * nir
+        assert np.abs(g - g_ref).max() <= fp64_elem * max(nir, 1e-300)
+        assert abs(e - e_ref) <= 1e-11 * max(scale, 1.0)
+    else:
+        bound = 2.0 ** -16 * abs_pair_force_sum(s, x)[:, None] + 1e-9 * nir
+        assert np.all(np.abs(g - g_ref) <= bound), np.abs(g - g_ref).max()
+        if nir >= 1.0:
+            assert abs(n2 - n2r) <= 1e-5 * n2r and abs(ni - nir) <= 1e-5 * nir
+    return e, g, e_ref, g_ref
+
+
+PRECS = ["fp64", "fp32"]
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lj_pair_minimum(prec):
+    sig, eps = 3.4, 0.15
+    r = 2 ** (1 / 6) * sig
+    s = make_system([[0, 0, 0], [r, 0.0, 0.0]], sigma=[sig, sig], eps=[eps, eps])
+    e, g = gpu_eval(s, s["x"], prec)
+    assert e == pytest.approx(-eps, rel=1e-12 if prec == "fp64" else 1e-6)
+    assert np.abs(g).max() < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_coulomb_and_mixing_pairs(prec):
+    s = make_system([[0.3, -1.0, 2.0], [4.1, 0.2, 1.1]], q=[0.4, -0.3], sigma=[3.1, 3.9], eps=[0.07, 0.19])
+    check(s, s["x"], prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_bonded_closed_forms(prec):
+    th = math.radians(131.0)
+    x = [[1.4, 0, 0], [0, 0, 0], [1.6 * math.cos(th), 1.6 * math.sin(th), 0]]
+    s = make_system(x, q=[0.3, 0.1, -0.4], eps=[0.1] * 3, angles=[[0, 1, 2]], angle_k=[50.0],
+                    angle_t0=[math.radians(109.5)], bonds=[[0, 1], [1, 2]], bond_k=[300.0, 250.0],
+                    bond_r0=[1.5, 1.45])
+    e, g, e_ref, _ = check(s, x, prec)
+    expect = 50.0 * (th - math.radians(109.5)) ** 2 + 300 * 0.1 ** 2 + 250 * 0.15 ** 2
+    assert e == pytest.approx(expect, rel=1e-12)
+
+
+@pytest.mark.parametrize("phi", [0.0, 60.0, 90.0, 180.0, -120.0])
+def test_torsion_energy(phi):
+    V = [1.3, -0.7, 0.45, 0.2]
+    s = make_system(dihedral_points(math.radians(phi)), dihedrals=[[0, 1, 2, 3]], dihedral_v=[V])
+    check(s, s["x"], "fp64", fp64_elem=1e-12)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_torsion_chain_all_terms(prec):
+    s = torsion_chain(150, 3)
+    check(s, s["x"], prec)
+
+
+# ------------------------------------------------------- workloads, sizes
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_chain512_start(prec):
+    s = config_system("chain512")
+    check(s, s["x"], prec)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (4, 3), (65, 4), (300, 5), (513, 6),
+                                    (1000, 7), (2100, 8), (4097, 9)])
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_sizes(n, seed, prec):
+    s = chain_system(n, seed)
+    check(s, s["x"], prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_relaxed_point(prec):
+    """A point 300 oracle L-BFGS iterations into the chain512 minimization:
+    no clashes, small gradient (the end-game regime)."""
+    s = config_system("chain512")
+    sysc = oracle.System(s)
+    res = oracle.minimize(lambda v: oracle.energy_grad(sysc, v.reshape(-1, 3)), s["x"].ravel(),
+                          oracle.MinParams(method=oracle.LBFGS, max_iter=300))
+    check(s, res.x, prec)
+
+
+def test_chain10k_full():
+    s = config_system("chain10k")
+    for prec in PRECS:
+        check(s, s["x"], prec)
+
+
+def test_chain50k_sampled():
+    """Full energy and sampled gradient rows at 50k atoms (the bench size)."""
+    s = config_system("chain50k")
+    e_ref, _ = oracle.energy_grad(s, s["x"], want_grad=False)
+    rng = np.random.default_rng(0)
+    atoms = np.unique(np.concatenate([[0, 1, 63, 64, 511, 512, 25_000, 49_998, 49_999],
+                                      rng.integers(0, 50_000, 40)]))
+    g_ref = oracle.atom_gradients(s, s["x"], atoms)
+    ctx = ff.Context(s, m_max=0)
+    for prec in PRECS:
+        e, g = gpu_eval(s, s["x"], prec, ctx)
+        assert abs(e - e_ref) <= 1e-6 * abs(e_ref), (prec, e, e_ref)
+        gs = g[atoms]
+        tol = 1e-10 if prec == "fp64" else 1e-5
+        assert np.abs(gs - g_ref).max() <= tol * np.abs(g_ref).max(), prec
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_clash_gives_nonfinite_not_error():
+    s = make_system([[0, 0, 0], [0, 0, 0], [3, 0, 0]], q=[0.1, 0.1, 0.1], eps=[0.1] * 3)
+    for prec in PRECS:
+        e, g = gpu_eval(s, s["x"], prec)
+        assert not math.isfinite(e)
+
+
+def test_no_pairs_at_all():
+    s = make_system([[0, 0, 0], [1.5, 0, 0], [2.0, 1.4, 0]], q=[0.3, -0.2, 0.4], eps=[0.1] * 3,
+                    bonds=[[0, 1], [1, 2]], bond_k=[300, 300], bond_r0=[1.5, 1.5], angles=[[0, 1, 2]],
+                    angle_k=[50], angle_t0=[1.9])
+    for prec in PRECS:
+        check(s, s["x"], prec)
+
+
+def test_deterministic_and_energy_only():
+    s = chain_system(3000, 4)
+    ctx = ff.Context(s, m_max=0)
+    xt = torch.tensor(s["x"], dtype=torch.float64, device="cuda")
+    for prec in PRECS:
+        e1, g1 = ctx.energy_grad(xt, prec)
+        e2, g2 = ctx.energy_grad(xt, prec)
+        e3, _ = ctx.energy_grad(xt, prec, want_grad=False)
+        torch.cuda.synchronize()
+        assert torch.equal(e1, e2) and torch.equal(g1, g2) and torch.equal(e1, e3)
+
+
+def test_rigid_motion_invariance_on_gpu():
+    s = chain_system(700, 12)
+    rng = np.random.default_rng(1)
+    from tests.systems import random_rotation
+    R = random_rotation(rng)
+    x2 = s["x"] @ R.T + rng.normal(size=3) * 20
+    e1, g1 = gpu_eval(s, s["x"], "fp64")
+    e2, g2 = gpu_eval(s, x2, "fp64")
+    assert e2 == pytest.approx(e1, rel=1e-10)
+    assert np.abs(g2 - g1 @ R.T).max() <= 1e-9 * np.abs(g1).max()
+    assert np.abs(g1.sum(0)).max() <= 1e-10 * np.abs(g1).sum()

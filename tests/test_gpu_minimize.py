@@ -1,0 +1,140 @@
+"""GPU minimizer parity against the FP64 CPU oracle, through the C ABI.
+
+FP64 mode follows the oracle iterate by iterate: same line-search decisions
+(equal evaluation counts), energies within 1e-9 relative and steps within
+1e-6 relative for the first 50 iterations.  FP32 mode is checked on its
+final state: the certified energy and gradient norm reported for the
+returned point must be what the oracle computes at that point.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1810_03358_amd as ff
+from synth import chain_system, config_system
+from tests.systems import make_system, torsion_chain
+
+pytestmark = pytest.mark.gpu
+
+OMETHOD = {"gd": oracle.GD, "fgm": oracle.FGM, "cg": oracle.CG, "lbfgs": oracle.LBFGS}
+
+
+def oracle_run(s, method, **kw):
+    sysc = oracle.System(s)
+    p = oracle.MinParams(method=OMETHOD[method], **kw)
+    return oracle.minimize(lambda v: oracle.energy_grad(sysc, v.reshape(-1, 3)), s["x"].ravel(), p)
+
+
+def gpu_run(s, method, ctx=None, x=None, **kw):
+    ctx = ctx or ff.Context(s, m_max=max(10, kw.get("m", 10)))
+    xt = torch.tensor(s["x"] if x is None else x, dtype=torch.float64, device="cuda").reshape(-1, 3).contiguous()
+    r = ctx.minimize(xt, method, **kw)
+    return r, xt.cpu().numpy(), ctx.trace(), ctx
+
+
+def compare_traces(tr, ref, n):
+    fr = np.array([t[0] for t in ref.trace[:n]])
+    hr = np.array([t[1] for t in ref.trace[:n]])
+    er = np.array([t[2] for t in ref.trace[:n]])
+    assert len(tr) >= len(fr)
+    np.testing.assert_array_equal(tr[: len(fr), 2], er)             # same LS decisions
+    np.testing.assert_allclose(tr[: len(fr), 0], fr, rtol=1e-9, atol=0)
+    np.testing.assert_allclose(tr[: len(fr), 1], hr, rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("method", ["lbfgs", "cg", "gd", "fgm"])
+def test_fp64_iterates_match_oracle_chain512(method):
+    s = config_system("chain512")
+    ref = oracle_run(s, method, max_iter=50)
+    r, x, tr, _ = gpu_run(s, method, max_iter=50, precision="fp64")
+    assert r["term"] == ref.term and r["iters"] == ref.iters and r["evals"] == ref.evals
+    compare_traces(tr, ref, 50)
+    assert r["energy"] == pytest.approx(ref.f, rel=1e-9)
+    assert np.abs(x.ravel() - ref.x).max() < 1e-6
+
+
+@pytest.mark.parametrize("method", ["lbfgs", "cg"])
+def test_fp64_iterates_torsion_chain(method):
+    s = torsion_chain(200, 5)
+    s["x"] = s["x"] + np.random.default_rng(2).normal(scale=0.2, size=s["x"].shape)
+    ref = oracle_run(s, method, max_iter=40, m=5)
+    r, x, tr, _ = gpu_run(s, method, max_iter=40, m=5, precision="fp64")
+    assert r["term"] == ref.term and r["iters"] == ref.iters
+    compare_traces(tr, ref, 40)
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_fp64_ls_par_more_trials(K):
+    s = chain_system(400, 21)
+    ref = oracle_run(s, "lbfgs", max_iter=25, ls_K=K)
+    r, x, tr, _ = gpu_run(s, "lbfgs", max_iter=25, ls_K=K)
+    assert r["evals"] == ref.evals
+    compare_traces(tr, ref, 25)
+
+
+def test_fp64_ls_h_for_lbfgs_and_ls_par_for_fgm():
+    s = chain_system(350, 22)
+    for method, ls in (("lbfgs", oracle.LS_H), ("fgm", oracle.LS_PAR)):
+        ref = oracle_run(s, method, max_iter=30, linesearch=ls)
+        r, x, tr, _ = gpu_run(s, method, max_iter=30, linesearch=ls)
+        assert r["evals"] == ref.evals, method
+        compare_traces(tr, ref, 30)
+
+
+def test_two_atom_lj_converges_to_the_closed_form_minimum():
+    sig, eps = 3.3, 0.2
+    s = make_system([[0, 0, 0], [1.5 * sig, 0.0, 0.0]], sigma=[sig, sig], eps=[eps, eps])
+    r, x, _, _ = gpu_run(s, "lbfgs", tol=1e-8, max_iter=200)
+    assert r["term"] == ff.FF_CONVERGED
+    assert np.linalg.norm(x[1] - x[0]) == pytest.approx(2 ** (1 / 6) * sig, rel=1e-6)
+    assert r["energy"] == pytest.approx(-eps, rel=1e-10)
+
+
+def test_termination_paths():
+    # coincident atoms: the start energy is not finite
+    s = make_system([[0, 0, 0], [0, 0, 0], [3, 0, 0]], q=[0.1, 0.1, 0.1], eps=[0.1] * 3)
+    r, _, _, _ = gpu_run(s, "lbfgs")
+    assert r["term"] == ff.FF_NONFINITE_START and r["evals"] == 1
+    # no iteration allowed
+    s = chain_system(100, 3)
+    r, x, _, _ = gpu_run(s, "cg", max_iter=0)
+    assert r["term"] == ff.FF_MAX_ITER and r["iters"] == 0 and r["evals"] == 1
+    np.testing.assert_array_equal(x, s["x"])
+    # one iteration
+    r, _, _, _ = gpu_run(s, "gd", max_iter=1)
+    assert r["term"] == ff.FF_MAX_ITER and r["iters"] == 1 and r["evals"] == 3
+
+
+def test_resume_continues_exactly():
+    s = chain_system(600, 8)
+    r20, x20, tr20, _ = gpu_run(s, "lbfgs", max_iter=20)
+    ctx = ff.Context(s, m_max=10)
+    xt = torch.tensor(s["x"], dtype=torch.float64, device="cuda")
+    ctx.minimize(xt, "lbfgs", max_iter=10)
+    r = ctx.minimize(xt, "lbfgs", max_iter=10, resume=True)
+    assert r["iters"] == 10
+    np.testing.assert_array_equal(xt.cpu().numpy(), x20)
+
+
+def test_fp32_mode_certifies_the_returned_point():
+    s = config_system("chain512")
+    r, x, _, _ = gpu_run(s, "lbfgs", max_iter=300, precision="fp32")
+    assert r["term"] in (ff.FF_MAX_ITER, ff.FF_CONVERGED, ff.FF_LS_FAILED)
+    e_ref, g_ref = oracle.energy_grad(s, x)
+    assert r["energy"] == pytest.approx(e_ref, rel=1e-9)
+    assert r["grad_inf"] == pytest.approx(np.abs(g_ref).max(), rel=1e-6)
+    ref = oracle_run(s, "lbfgs", max_iter=300)
+    # both runs descend from 1e13 to the same energy scale
+    assert r["energy"] < 0 and abs(r["energy"] - ref.f) < 0.05 * abs(ref.f)
+
+
+def test_fp32_converges_with_fp64_end_game():
+    s = chain_system(120, 31)
+    r, x, _, _ = gpu_run(s, "lbfgs", max_iter=5000, precision="fp32")
+    assert r["term"] == ff.FF_CONVERGED
+    assert r["evals_fp64"] >= 1
+    e_ref, g_ref = oracle.energy_grad(s, x)
+    assert np.abs(g_ref).max() < 1e-3
