@@ -160,6 +160,13 @@ ff_status ff_minimize(ff_ctx *ctx, double *xyz_inout, const ff_min_params *param
  * written or a negative ff_status.  Blocks on `stream`. */
 int32_t ff_get_trace(ff_ctx *ctx, double *host_out, int32_t max_entries, void *stream);
 
+/* Measurement helper: average duration in milliseconds of `reps`
+ * back-to-back launches of the nonbonded pair kernel alone at xyz (device),
+ * timed with HIP events recorded on `stream`.  Overwrites the workspace's
+ * partial-sum buffers; blocks until done. */
+ff_status ff_time_pair(ff_ctx *ctx, const double *xyz, int32_t precision, int32_t reps,
+                       void *stream, double *avg_ms);
+
 /* Fill the defaults listed in ff_min_params. */
 void ff_default_params(ff_min_params *params);
 

@@ -140,6 +140,14 @@ class Context:
         return dict(term=r.term, term_name=TERMS.get(r.term, str(r.term)), iters=r.iters, evals=r.evals,
                     evals_fp64=r.evals_fp64, energy=r.energy, grad_inf=r.grad_inf, grad_2=r.grad_2)
 
+    def time_pair(self, x: torch.Tensor, precision: str | int = "fp32", reps: int = 20, stream=None) -> float:
+        """Average duration (ms) of the pair kernel alone at x, HIP-event timed."""
+        x = self._coords(x)
+        ms = C.c_double()
+        _check(N.load().ff_time_pair(self._ctx, C.c_void_p(x.data_ptr()), int(PRECISIONS.get(precision, precision)),
+                                     reps, _stream_ptr(stream), C.byref(ms)), "ff_time_pair")
+        return ms.value
+
     def trace(self, max_entries: int = 4096, stream=None) -> np.ndarray:
         """(E, h, evals) after each iteration of the last minimize call."""
         buf = np.zeros(3 * max_entries)

@@ -45,7 +45,7 @@ class FFMinResult(C.Structure):
 
 
 EXPORTS = ("ff_workspace_bytes", "ff_create", "ff_destroy", "ff_energy_grad", "ff_minimize",
-           "ff_get_trace", "ff_default_params", "ff_last_error")
+           "ff_get_trace", "ff_time_pair", "ff_default_params", "ff_last_error")
 
 _lib = None
 
@@ -72,6 +72,8 @@ def load():
     lib.ff_minimize.restype = C.c_int
     lib.ff_get_trace.argtypes = [C.c_void_p, _dp, C.c_int32, C.c_void_p]
     lib.ff_get_trace.restype = C.c_int32
+    lib.ff_time_pair.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, _dp]
+    lib.ff_time_pair.restype = C.c_int
     lib.ff_default_params.argtypes = [C.POINTER(FFMinParams)]
     lib.ff_default_params.restype = None
     lib.ff_last_error.argtypes = []

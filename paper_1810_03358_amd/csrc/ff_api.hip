@@ -461,6 +461,37 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     return FF_OK;
 }
 
+// Average duration (ms) of `reps` back-to-back launches of the pair kernel
+// alone at xyz, timed with HIP events recorded on the launch stream.
+ff_status ff_time_pair(ff_ctx* c, const double* xyz, int32_t precision, int32_t reps, void* stream,
+                       double* avg_ms) {
+    g_err.clear();
+    if (!c || !xyz || !avg_ms || reps < 1) return fail(FF_ERR_ARG, "bad arguments");
+    if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision");
+    hipStream_t st = stream ? (hipStream_t)stream : c->own;
+    Args a{};
+    a.L = c->L;
+    a.ws = c->ws;
+    a.xyz_in = xyz;
+    a.direct = 1;
+    a.direct_prec = precision;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(FF_ERR_HIP, "event"); }
+    hipError_t e = launch_pair(a, precision, st);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pair(a, precision, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(FF_ERR_HIP, "pair timing: %s", hipGetErrorString(e));
+    *avg_ms = (double)ms / reps;
+    return FF_OK;
+}
+
 // Per-iteration trace of the last ff_minimize call: out[3k..3k+2] = (E after
 // iteration k, accepted step h, evaluations so far).  Returns the number of
 // entries written (at most max_entries), or a negative ff_status.
