@@ -71,9 +71,18 @@ static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
     if (m_max < 0 || m_max > kMaxM) return false;
     L.n = s->n_atoms;
     L.np = (L.n + kAtomAlign - 1) / kAtomAlign * kAtomAlign;
-    if (L.np <= 2048) { L.cfg = 0; L.block = 64; L.chunk = 2; }
-    else if (L.np <= 16384) { L.cfg = 1; L.block = 256; L.chunk = 4; }
-    else { L.cfg = 2; L.block = 512; L.chunk = 8; }
+    if (L.np <= 2048) { L.cfg = 0; L.chunk = 2; }
+    else if (L.np <= 16384) { L.cfg = 1; L.chunk = 4; }
+    else { L.cfg = 2; L.chunk = 8; }
+    // tuning override "cfg[,chunk]" (read when the workspace is sized and
+    // when it is created, so both agree)
+    if (const char* env = std::getenv("FF_PAIR_CONFIG")) {
+        int cfg = -1, chunk = 0;
+        const int got = std::sscanf(env, "%d,%d", &cfg, &chunk);
+        if (got >= 1 && cfg >= 0 && cfg < kNumTileConfigs) L.cfg = cfg;
+        if (got == 2 && chunk >= 1 && chunk <= 4096) L.chunk = chunk;
+    }
+    L.block = kTileConfigs[L.cfg].block;
     L.nb = L.np / L.block;
     L.nt = L.np / kTile;
     L.n_units = 0;
@@ -91,6 +100,7 @@ static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
     const int n_terms = L.n_bonds + L.n_angles + L.n_dihedrals;
     L.n_bonded_blocks = std::max(1, (n_terms + kBondedPerBlock - 1) / kBondedPerBlock);
     L.n_fin_blocks = (L.n + kFinBlock - 1) / kFinBlock;
+    L.accept_bx = std::max(1, std::min(64, (3 * L.n + 8 * kFinBlock - 1) / (8 * kFinBlock)));
     L.m_max = m_max;
     L.vstride = (3 * (size_t)L.np + 31) / 32 * 32;
     size_t o = 0;
@@ -120,7 +130,8 @@ static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
     L.off_inc_start = take((np + 1) * 4);
     L.off_inc = take((size_t)L.n_terms_slots * 4);
     const size_t vec_blocks = (3 * np + kFinBlock - 1) / kFinBlock;
-    L.off_red = take(std::max(vec_blocks * kMaxDots, (size_t)L.n_fin_blocks * 3) * 8);
+    L.off_red = take(std::max({vec_blocks * 3, (size_t)L.accept_bx * (kMaxM + 1) * 6,
+                               (size_t)L.n_fin_blocks * 3}) * 8);
     L.off_vec = take((size_t)V_COUNT * L.vstride * 8 + (size_t)kTraceCap * 3 * 8);
     L.total = o;
     return true;

@@ -123,6 +123,22 @@ struct Ctl {
     uint32_t ticket_fin, ticket_acc, ticket_prep;
 };
 
+// ------------------------------------------------------- pair tile configs
+// I-block of `block` atoms; the FP32 and FP64 kernels split it into
+// waves x 64 lanes x ipl atoms per lane.  Both precisions of one
+// configuration share the block size, hence one chunk table.
+struct TileConfig { int block, waves32, ipl32, waves64, ipl64; };
+constexpr TileConfig kTileConfigs[] = {
+    {64, 1, 1, 1, 1},     // 0
+    {256, 4, 1, 4, 1},    // 1
+    {512, 4, 2, 8, 1},    // 2
+    {512, 8, 1, 8, 1},    // 3
+    {256, 2, 2, 4, 1},    // 4
+    {128, 2, 1, 2, 1},    // 5
+    {128, 1, 2, 2, 1},    // 6
+};
+constexpr int kNumTileConfigs = sizeof(kTileConfigs) / sizeof(kTileConfigs[0]);
+
 // ------------------------------------------------------------- tile tables
 struct ChunkInfo {        // one workgroup of the pair kernel
     int32_t row;          // I-block index
@@ -140,6 +156,7 @@ struct Layout {
     int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;
     int32_t n_bonds, n_angles, n_dihedrals, n_terms_slots, n_bonded_blocks;
     int32_t n_fin_blocks;
+    int32_t accept_bx;        // x-extent of the accept pass grid
     int32_t m_max;
     int32_t cfg;              // tile configuration index
     size_t vstride;           // doubles between vectors

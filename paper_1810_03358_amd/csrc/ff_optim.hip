@@ -78,6 +78,29 @@ __device__ __forceinline__ double block_sum_array(const double* p, int n, bool i
 }
 
 // ------------------------------------------------------------------ finalize
+// Pair part of the gradient of `atom`: the i-side partials of every chunk of
+// its I-block, then the j-side partials of every unit that holds its j-tile,
+// in a fixed order.  T is the storage type of the partials (FP32 mode: float).
+template <typename T>
+__device__ __forceinline__ void gather_pair(const Args& a, int atom, double& gx, double& gy, double& gz) {
+    const Layout& L = a.L;
+    const int row = atom / L.block, il = atom - row * L.block;
+    const int t = atom / kTile, jl = atom - t * kTile;
+    const RowInfo* R = at<RowInfo>(a.ws, L.off_rows);
+    const T* Pi = at<T>(a.ws, L.off_pi);
+    const T* Pj = at<T>(a.ws, L.off_pj);
+    const RowInfo ri = R[row];
+    for (int ch = ri.chunk_start; ch < ri.chunk_start + ri.n_chunks; ++ch) {
+        const T* p = Pi + ((size_t)ch * L.block + il) * 3;
+        gx += (double)p[0]; gy += (double)p[1]; gz += (double)p[2];
+    }
+    for (int r = 0; r <= row; ++r) {
+        const RowInfo rr = R[r];
+        const T* p = Pj + ((size_t)(rr.unit_start + t - rr.t0) * kTile + jl) * 3;
+        gx += (double)p[0]; gy += (double)p[1]; gz += (double)p[2];
+    }
+}
+
 // One thread per atom: gradient = sum of the pair partials of its I-block
 // (all chunks of its row), of the j partials of every unit holding it, and
 // of its bonded-term slots.  Then |g|_inf, |g|^2, optionally <g_base, d>, and
@@ -91,21 +114,9 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     const int atom = blockIdx.x * kFinBlock + threadIdx.x;
     double gx = 0.0, gy = 0.0, gz = 0.0;
     if (atom < L.n) {
-        const int row = atom / L.block, il = atom - row * L.block;
-        const int t = atom / kTile, jl = atom - t * kTile;
-        const RowInfo* R = at<RowInfo>(a.ws, L.off_rows);
-        const double* Pi = at<double>(a.ws, L.off_pi);
-        const double* Pj = at<double>(a.ws, L.off_pj);
-        const RowInfo ri = R[row];
-        for (int ch = ri.chunk_start; ch < ri.chunk_start + ri.n_chunks; ++ch) {
-            const double* p = Pi + ((size_t)ch * L.block + il) * 3;
-            gx += p[0]; gy += p[1]; gz += p[2];
-        }
-        for (int r = 0; r <= row; ++r) {
-            const RowInfo rr = R[r];
-            const double* p = Pj + ((size_t)(rr.unit_start + t - rr.t0) * kTile + jl) * 3;
-            gx += p[0]; gy += p[1]; gz += p[2];
-        }
+        const bool p32 = a.direct ? a.direct_prec == 1 : c->prec == 1;
+        if (p32) gather_pair<float>(a, atom, gx, gy, gz);
+        else gather_pair<double>(a, atom, gx, gy, gz);
         const int* inc0 = at<int>(a.ws, L.off_inc_start);
         const int* inc = at<int>(a.ws, L.off_inc);
         const double* FB = at<double>(a.ws, L.off_fb);
@@ -193,63 +204,88 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
 // -------------------------------------------------------------------- accept
 // After a successful line search: method-specific vectors and dot products.
 //  CG:     <g_new, g_old>, <g_new, r_old>
-//  L-BFGS: s = x_new - x_old and y = g_new - g_old into the spare history
-//          vectors, then <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for every
-//          stored pair i, <s,S_i> <s,Y_i> <y,S_i> <y,Y_i> <g,S_i> <g,Y_i>.
+//  L-BFGS: s = x_new - x_old and y = g_new - g_old (written to the spare
+//          history vectors), <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for
+//          every stored pair i, <s,S_i> <s,Y_i> <y,S_i> <y,Y_i> <g,S_i> <g,Y_i>.
+// Grid: (accept_bx, kMaxM + 1).  Row 0 computes the first group of six, row
+// r >= 1 the six products with stored pair r-1 (s and y are recomputed from
+// the point vectors in every row, with the same arithmetic); each block
+// strides over its share of the 3N elements and reduces once.  The last
+// block sums the per-block partials of every dot in block order.
 __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
     Ctl* c = ctl_rw(a);
     if (!c->accept) return;
     const int n3 = 3 * a.L.n;
-    const int i = blockIdx.x * kFinBlock + threadIdx.x;
-    const bool in = i < n3;
     const int method = c->p.method;
+    const int row = blockIdx.y;
+    const int nh = method == M_LBFGS ? c->hist_n : 0;
+    const bool active = (method == M_LBFGS && row <= nh) || (method == M_CG && row == 0);
     double* red = at<double>(a.ws, a.L.off_red);
-    int nd = 0;
-    if (method == M_CG) {
-        nd = 2;
-        double v[2] = {0.0, 0.0};
-        if (in) {
-            const double gn = vec(a, V_G0 + c->acc_new)[i];
-            v[0] = gn * vec(a, V_G0 + c->acc_old)[i];
-            v[1] = gn * vec(a, V_R)[i];
+    const int nbx = gridDim.x;
+    if (active) {
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const double* xn = vec(a, V_X0 + c->acc_new);
+        const double* xo = vec(a, V_X0 + c->acc_old);
+        const double* gn = vec(a, V_G0 + c->acc_new);
+        const double* go = vec(a, V_G0 + c->acc_old);
+        const int stride = nbx * kFinBlock;
+        if (method == M_CG) {
+            const double* r = vec(a, V_R);
+            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+                v[0] += gn[i] * go[i];
+                v[1] += gn[i] * r[i];
+            }
+        } else if (row == 0) {
+            double* ss = vec(a, c->spare_s);
+            double* yy = vec(a, c->spare_y);
+            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+                const double s = __dsub_rn(xn[i], xo[i]);
+                const double g = gn[i];
+                const double y = __dsub_rn(g, go[i]);
+                ss[i] = s;
+                yy[i] = y;
+                v[0] += s * y; v[1] += y * y; v[2] += s * s;
+                v[3] += g * s; v[4] += g * y; v[5] += g * g;
+            }
+        } else {
+            const double* S = vec(a, c->hist_s[row - 1]);
+            const double* Y = vec(a, c->hist_y[row - 1]);
+            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+                const double s = __dsub_rn(xn[i], xo[i]);
+                const double g = gn[i];
+                const double y = __dsub_rn(g, go[i]);
+                const double Si = S[i], Yi = Y[i];
+                v[0] += s * Si; v[1] += s * Yi; v[2] += y * Si;
+                v[3] += y * Yi; v[4] += g * Si; v[5] += g * Yi;
+            }
         }
-        double tot[2];
-        block_reduce<2>(v, false, tot);
-        if (threadIdx.x == 0) { red[nd * blockIdx.x] = tot[0]; red[nd * blockIdx.x + 1] = tot[1]; }
-    } else if (method == M_LBFGS) {
-        const int nh = c->hist_n;
-        nd = 6 + 6 * nh;
-        double s = 0.0, y = 0.0, g = 0.0;
-        if (in) {
-            s = __dsub_rn(vec(a, V_X0 + c->acc_new)[i], vec(a, V_X0 + c->acc_old)[i]);
-            g = vec(a, V_G0 + c->acc_new)[i];
-            y = __dsub_rn(g, vec(a, V_G0 + c->acc_old)[i]);
-            vec(a, c->spare_s)[i] = s;
-            vec(a, c->spare_y)[i] = y;
-        }
-        double v6[6] = {s * y, y * y, s * s, g * s, g * y, g * g};
         double tot[6];
-        block_reduce<6>(v6, false, tot);
-        if (threadIdx.x == 0) for (int k = 0; k < 6; ++k) red[nd * blockIdx.x + k] = tot[k];
-        for (int h = 0; h < nh; ++h) {
-            double S = 0.0, Y = 0.0;
-            if (in) { S = vec(a, c->hist_s[h])[i]; Y = vec(a, c->hist_y[h])[i]; }
-            double w6[6] = {s * S, s * Y, y * S, y * Y, g * S, g * Y};
-            block_reduce<6>(w6, false, tot);
-            if (threadIdx.x == 0) for (int k = 0; k < 6; ++k) red[nd * blockIdx.x + 6 + 6 * h + k] = tot[k];
-        }
+        block_reduce<6>(v, false, tot);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 6; ++k) red[((size_t)row * nbx + blockIdx.x) * 6 + k] = tot[k];
     }
-    if (!last_block(&c->ticket_acc)) return;
+    // every block takes a ticket; the last one finishes the reduction
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = atomicAdd(&c->ticket_acc, 1u);
+        is_last = (t == gridDim.x * gridDim.y - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
     __shared__ double dots[kMaxDots];
-    for (int k = 0; k < nd; ++k) {
+    const int nd = method == M_LBFGS ? 6 * (nh + 1) : (method == M_CG ? 2 : 0);
+    for (int k = threadIdx.x; k < nd; k += kFinBlock) {
+        const int r = k / 6, q = k - 6 * r;
         double acc = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += kFinBlock) acc += red[nd * b + k];
-        double arr[1] = {acc}, out[1];
-        block_reduce<1>(arr, false, out);
-        if (threadIdx.x == 0) dots[k] = out[0];
+        for (int b = 0; b < nbx; ++b) acc += red[((size_t)r * nbx + b) * 6 + q];
+        dots[k] = acc;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    c->ticket_acc = 0u;
     after_accept(c, dots);
 }
 
@@ -322,7 +358,7 @@ hipError_t launch_finalize(const Args& a, hipStream_t s) {
 hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s) {
     const int blocks = (3 * a.L.n + kFinBlock - 1) / kFinBlock;
     if (which == 0) hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(kFinBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_accept, dim3(blocks), dim3(kFinBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_accept, dim3(a.L.accept_bx, kMaxM + 1), dim3(kFinBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -28,17 +28,21 @@
 
 namespace ff {
 
+#ifndef UNROLL32
+#define UNROLL32 4    // unroll of the 64-step j loop (FP32 kernel)
+#endif
+
 #ifndef FF_DPP_ROTATE
 #define FF_DPP_ROTATE 0x134   // wave_rol:1 -- lane l receives lane (l+1) mod 64
 #endif
 
 __device__ __forceinline__ float rotate_down(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), FF_DPP_ROTATE, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), FF_DPP_ROTATE, 0xF, 0xF, false));
 }
 __device__ __forceinline__ double rotate_down(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), FF_DPP_ROTATE, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), FF_DPP_ROTATE, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), FF_DPP_ROTATE, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), FF_DPP_ROTATE, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -186,13 +190,13 @@ __global__ void __launch_bounds__(kBondedPerBlock) k_bonded(Args a) {
 
 // ---------------------------------------------------------------- FP32 pairs
 
+// i-atoms of one lane: high halves of the coordinates and the per-atom
+// factors stay in registers; the low halves live in LDS (s_ilo) because only
+// the rare close-pair path reads them.
 template <int IPL>
 struct IAtoms32 {
-    float xh[IPL], yh[IPL], zh[IPL];     // high halves
-    float xl[IPL], yl[IPL], zl[IPL];     // low halves
+    float xh[IPL], yh[IPL], zh[IPL];
     float c12[IPL], c6[IPL], q[IPL];
-    uint64_t excl[IPL];
-    int32_t idx[IPL];
 };
 
 // A pair closer than sqrt(kCorrR2) by the high halves: redo the displacement
@@ -200,13 +204,13 @@ struct IAtoms32 {
 // in FP64 (clash energies reach 1e15 kcal/mol at the start of a minimization)
 // and the FP32 path is switched off for it by r2 = inf.
 template <int IPL>
-__device__ __forceinline__ void close_pair32(const IAtoms32<IPL>& I, int k, float4 pj, float4 lo, float2 cj,
-                                          float& dx, float& dy, float& dz, float& r2,
+__device__ __forceinline__ void close_pair32(const IAtoms32<IPL>& I, int k, float4 pj, float4 lo, float4 ilo,
+                                          float2 cj, float& dx, float& dy, float& dz, float& r2,
                                           double& gx, double& gy, double& gz, double& e64,
                                           float& fjx, float& fjy, float& fjz) {
-    const double ddx = ((double)pj.x - (double)I.xh[k]) + ((double)lo.x - (double)I.xl[k]);
-    const double ddy = ((double)pj.y - (double)I.yh[k]) + ((double)lo.y - (double)I.yl[k]);
-    const double ddz = ((double)pj.z - (double)I.zh[k]) + ((double)lo.z - (double)I.zl[k]);
+    const double ddx = ((double)pj.x - (double)I.xh[k]) + ((double)lo.x - (double)ilo.x);
+    const double ddy = ((double)pj.y - (double)I.yh[k]) + ((double)lo.y - (double)ilo.y);
+    const double ddz = ((double)pj.z - (double)I.zh[k]) + ((double)lo.z - (double)ilo.z);
     const double rr = ddx * ddx + ddy * ddy + ddz * ddz;
     if (rr < kClashR2) {
         const double rinv = 1.0 / sqrt(rr);
@@ -226,14 +230,20 @@ __device__ __forceinline__ void close_pair32(const IAtoms32<IPL>& I, int k, floa
     }
 }
 
-template <int IPL, bool MASKED>
+template <int IPL, bool MASKED, bool CHECK>
 __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const float2* __restrict__ s_c,
-                                       const float4* __restrict__ s_lo, int lane, int J0,
+                                       const float4* __restrict__ s_lo, const float4* __restrict__ s_ilo,
+                                       int lane, int il0, int i0, int J0, const uint64_t* __restrict__ EX,
                                        const IAtoms32<IPL>& I, float (&fx)[IPL], float (&fy)[IPL],
                                        float (&fz)[IPL], double (&gx)[IPL], double (&gy)[IPL],
                                        double (&gz)[IPL], float& fjx, float& fjy, float& fjz,
                                        float& e32, double& e64) {
-#pragma unroll 4
+    uint64_t excl[IPL];
+    if (MASKED) {
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) excl[k] = EX[i0 + k * 64];
+    }
+#pragma unroll UNROLL32
     for (int s = 0; s < kTile; ++s) {
         const int js = lane + s;
         const float4 pj = s_xq[js];
@@ -245,13 +255,14 @@ __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const fl
             float dz = pj.z - I.zh[k];
             float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
             if (MASKED) {
-                const int delta = J0 + (js & (kTile - 1)) - I.idx[k];
+                const int delta = J0 + (js & (kTile - 1)) - (i0 + k * 64);
                 const unsigned dm1 = (unsigned)(delta - 1);
-                const bool excl = dm1 < (unsigned)kExclWindow && ((I.excl[k] >> (dm1 & 63u)) & 1ull);
-                r2 = (delta > 0 && !excl) ? r2 : __builtin_inff();
+                const bool ex = dm1 < (unsigned)kExclWindow && ((excl[k] >> (dm1 & 63u)) & 1ull);
+                r2 = (delta > 0 && !ex) ? r2 : __builtin_inff();
             }
-            if (r2 < kCorrR2)
-                close_pair32<IPL>(I, k, pj, s_lo[js], cj, dx, dy, dz, r2, gx[k], gy[k], gz[k], e64, fjx, fjy, fjz);
+            if (CHECK && r2 < kCorrR2)
+                close_pair32<IPL>(I, k, pj, s_lo[js], s_ilo[il0 + k * 64], cj, dx, dy, dz, r2, gx[k], gy[k],
+                                  gz[k], e64, fjx, fjy, fjz);
             const float rinv = __builtin_amdgcn_rsqf(r2);
             const float rinv2 = rinv * rinv;
             const float rinv6 = rinv2 * rinv2 * rinv2;
@@ -272,6 +283,17 @@ __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const fl
         fjy = rotate_down(fjy);
         fjz = rotate_down(fjz);
     }
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
 __device__ __forceinline__ void split(double v, float& hi, float& lo) {
@@ -309,19 +331,38 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
 
     IAtoms32<IPL> I;
     double gx[IPL], gy[IPL], gz[IPL];
+    __shared__ float4 s_ilo[B];
+    const int il0 = wave * 64 * IPL + lane;     // local index of this lane's first i-atom
+    const int i0 = I0 + il0;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        const int i = I0 + wave * 64 * IPL + k * 64 + lane;
+        const int i = i0 + k * 64;
         double p[3];
         load_pos(X, i, n, p);
-        split(p[0], I.xh[k], I.xl[k]);
-        split(p[1], I.yh[k], I.yl[k]);
-        split(p[2], I.zh[k], I.zl[k]);
+        float4 lo;
+        split(p[0], I.xh[k], lo.x);
+        split(p[1], I.yh[k], lo.y);
+        split(p[2], I.zh[k], lo.z);
+        lo.w = 0.0f;
+        s_ilo[il0 + k * 64] = lo;
         I.c12[k] = C12[i]; I.c6[k] = C6[i]; I.q[k] = Q[i];
-        I.excl[k] = EX[i];
-        I.idx[k] = i;
         gx[k] = gy[k] = gz[k] = 0.0;
     }
+    // bounding box of this wave's i-atoms: a j-tile whose box is farther than
+    // sqrt(kCorrR2) cannot hold a close pair, so it runs the unchecked body
+    float ib[6];
+    ib[0] = ib[3] = I.xh[0];
+    ib[1] = ib[4] = I.yh[0];
+    ib[2] = ib[5] = I.zh[0];
+#pragma unroll
+    for (int k = 1; k < IPL; ++k) {
+        ib[0] = fminf(ib[0], I.xh[k]); ib[3] = fmaxf(ib[3], I.xh[k]);
+        ib[1] = fminf(ib[1], I.yh[k]); ib[4] = fmaxf(ib[4], I.yh[k]);
+        ib[2] = fminf(ib[2], I.zh[k]); ib[5] = fmaxf(ib[5], I.zh[k]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { ib[c] = wave_minf(ib[c]); ib[3 + c] = wave_maxf(ib[3 + c]); }
+    __shared__ float s_jbox[6];
     __shared__ float4 s_xq[2 * kTile];
     __shared__ float2 s_c[2 * kTile];
     __shared__ float4 s_lo[2 * kTile];
@@ -345,16 +386,31 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
             s_xq[threadIdx.x] = h; s_xq[threadIdx.x + kTile] = h;
             s_lo[threadIdx.x] = l; s_lo[threadIdx.x + kTile] = l;
             s_c[threadIdx.x] = c;  s_c[threadIdx.x + kTile] = c;
+            const float b0 = wave_minf(h.x), b1 = wave_minf(h.y), b2 = wave_minf(h.z);
+            const float b3 = wave_maxf(h.x), b4 = wave_maxf(h.y), b5 = wave_maxf(h.z);
+            if (threadIdx.x == 0) {
+                s_jbox[0] = b0; s_jbox[1] = b1; s_jbox[2] = b2;
+                s_jbox[3] = b3; s_jbox[4] = b4; s_jbox[5] = b5;
+            }
         }
         __syncthreads();
         float fx[IPL], fy[IPL], fz[IPL];
 #pragma unroll
         for (int k = 0; k < IPL; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
         float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, e32 = 0.0f;
+        const float gxb = fmaxf(0.0f, fmaxf(s_jbox[0] - ib[3], ib[0] - s_jbox[3]));
+        const float gyb = fmaxf(0.0f, fmaxf(s_jbox[1] - ib[4], ib[1] - s_jbox[4]));
+        const float gzb = fmaxf(0.0f, fmaxf(s_jbox[2] - ib[5], ib[2] - s_jbox[5]));
+        const bool far = gxb * gxb + gyb * gyb + gzb * gzb >= kCorrR2;
         if (t < t_masked_end)
-            tile32<IPL, true>(s_xq, s_c, s_lo, lane, J0, I, fx, fy, fz, gx, gy, gz, fjx, fjy, fjz, e32, e64);
+            tile32<IPL, true, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, I, fx, fy, fz, gx, gy, gz,
+                                    fjx, fjy, fjz, e32, e64);
+        else if (!far)
+            tile32<IPL, false, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, I, fx, fy, fz, gx, gy, gz,
+                                     fjx, fjy, fjz, e32, e64);
         else
-            tile32<IPL, false>(s_xq, s_c, s_lo, lane, J0, I, fx, fy, fz, gx, gy, gz, fjx, fjy, fjz, e32, e64);
+            tile32<IPL, false, false>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, I, fx, fy, fz, gx, gy, gz,
+                                      fjx, fjy, fjz, e32, e64);
 #pragma unroll
         for (int k = 0; k < IPL; ++k) { gx[k] += fx[k]; gy[k] += fy[k]; gz[k] += fz[k]; }
         e64 += e32;
@@ -370,15 +426,17 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
                 sy += (double)s_fj[w][1][lane];
                 sz += (double)s_fj[w][2][lane];
             }
-            double* pj = at<double>(a.ws, L.off_pj) + ((size_t)(ch.unit_base + t - ch.t_begin) * kTile + lane) * 3;
-            pj[0] = sx; pj[1] = sy; pj[2] = sz;
+            float* pj = at<float>(a.ws, L.off_pj) + ((size_t)(ch.unit_base + t - ch.t_begin) * kTile + lane) * 3;
+            pj[0] = (float)sx; pj[1] = (float)sy; pj[2] = (float)sz;
         }
     }
-    double* pi = at<double>(a.ws, L.off_pi) + (size_t)wg * B * 3;
+    // FP32 mode stores its partial sums in single precision (they are FP32
+    // tile sums already); the finalize adds them up in FP64
+    float* pi = at<float>(a.ws, L.off_pi) + (size_t)wg * B * 3;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int il = wave * 64 * IPL + k * 64 + lane;
-        pi[3 * il] = gx[k]; pi[3 * il + 1] = gy[k]; pi[3 * il + 2] = gz[k];
+        pi[3 * il] = (float)gx[k]; pi[3 * il + 1] = (float)gy[k]; pi[3 * il + 2] = (float)gz[k];
     }
     block_energy_store<WAVES>(e64, at<double>(a.ws, L.off_ep) + wg);
 }
@@ -503,21 +561,26 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
 // ------------------------------------------------------------- host launch
 // Tile configurations (index = Layout::cfg): I-block of B = 64 * waves * ipl
 // atoms.  Both precisions use the same B so that they share one chunk table.
+#define FF_PAIR_CASE(ID)                                                                           \
+    case ID: {                                                                                     \
+        constexpr TileConfig T = kTileConfigs[ID];                                                 \
+        if (prec) hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
+        else hipLaunchKernelGGL((k_pair64<T.waves64, T.ipl64>), dim3(grid), dim3(64 * T.waves64), 0, s, a);     \
+        break;                                                                                     \
+    }
+
 hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
     const int grid = a.L.n_chunks;
     switch (a.L.cfg) {
-    case 0:   // B = 64
-        if (prec) hipLaunchKernelGGL((k_pair32<1, 1>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_pair64<1, 1>), dim3(grid), dim3(64), 0, s, a);
-        break;
-    case 1:   // B = 256
-        if (prec) hipLaunchKernelGGL((k_pair32<4, 1>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_pair64<4, 1>), dim3(grid), dim3(256), 0, s, a);
-        break;
-    default:  // B = 512
-        if (prec) hipLaunchKernelGGL((k_pair32<4, 2>), dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_pair64<8, 1>), dim3(grid), dim3(512), 0, s, a);
-        break;
+        FF_PAIR_CASE(0)
+        FF_PAIR_CASE(1)
+        FF_PAIR_CASE(2)
+        FF_PAIR_CASE(3)
+        FF_PAIR_CASE(4)
+        FF_PAIR_CASE(5)
+        FF_PAIR_CASE(6)
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
