@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: every system here is minimized on a single device "
@@ -78,6 +80,14 @@ def main():
     n = s["n_atoms"]
     pairs = non_excluded_pairs(n)
     stream = torch.cuda.Stream(device=dev)      # default priority
+    if args.copy_calibration:
+        # a kernel of known traffic: reads and writes exactly 256 MiB
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     with torch.cuda.stream(stream):
         ctx = ff.Context(s, m_max=10, device=dev, stream=stream)
         x = torch.tensor(s["x"], dtype=torch.float64, device=dev).contiguous()

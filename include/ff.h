@@ -66,6 +66,13 @@ typedef enum {
     FF_NONFINITE_START = 3    /* E or grad E not finite at the start point */
 } ff_term;
 
+/* beta of the CG variants named in section 5.1 (y = g_{k+1} - g_k, d = the
+ * previous unnormalized direction): PRP <g+,y>/|g|^2, FR |g+|^2/|g|^2,
+ * HS <g+,y>/<d,y>, PRP+ max(0, PRP), CD |g+|^2/(-<d,g>), LS <g+,y>/(-<d,g>),
+ * DY |g+|^2/<d,y>.  A zero or non-finite denominator restarts (beta = 0). */
+typedef enum { FF_CG_PRP = 0, FF_CG_FR = 1, FF_CG_HS = 2, FF_CG_PRP_PLUS = 3,
+               FF_CG_CD = 4, FF_CG_LS = 5, FF_CG_DY = 6 } ff_cg_beta;
+
 /* Line searches of section 5.2: LS_PAR (Algorithm 6), LS_H (Algorithm 5). */
 typedef enum { FF_LS_DEFAULT = -1, FF_LS_PAR = 0, FF_LS_H = 1 } ff_linesearch;
 
@@ -111,6 +118,14 @@ typedef struct {
     double eps_h;         /* LS_H gives up below this step, A [1e-10] */
     int32_t cg_restart;   /* CG restarts from -g every cg_restart iterations; 0: 3N [0] */
     int32_t flags;        /* FF_MIN_* [0] */
+    int32_t cg_beta;      /* ff_cg_beta [FF_CG_PRP] */
+    int32_t ls_par_g0;    /* Algorithm 6's G0: 1 = first parabola from f and the
+                             slope at the base point, 0 = symmetric trials
+                             -h0/2, +h0/2 (steps may then be negative) [1] */
+    int32_t fgm_restart;  /* 1: FGM restarts its momentum (theta = 1) whenever an
+                             iterate's energy exceeds the previous one
+                             (function-value adaptive restart); 0: Algorithm 1
+                             as printed [0] */
 } ff_min_params;
 
 /* Outcome of ff_minimize (host struct). */

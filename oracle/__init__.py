@@ -16,6 +16,7 @@ shares no code with the HIP path.
 from .energy import System, energy_grad, energy_terms, atom_gradients, num_threads, build  # noqa: F401
 from .minimize import (  # noqa: F401
     MinParams, MinResult, minimize, ls_par, ls_h, lbfgs_direction, fgm_coefficients,
-    GD, FGM, CG, LBFGS, LS_PAR, LS_H,
+    GD, FGM, CG, LBFGS, LS_PAR, LS_H, cg_beta,
+    CG_PRP, CG_FR, CG_HS, CG_PRP_PLUS, CG_CD, CG_LS, CG_DY,
     CONVERGED, MAX_ITER, LS_FAILED, NONFINITE_START,
 )

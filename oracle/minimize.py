@@ -29,11 +29,18 @@ the rule the GPU library implements as well):
   -g (CG: r = -g; L-BFGS: history cleared), FGM restarts its momentum once
   (x^{k-1} = x^k, theta = 1), and otherwise the run stops with LS_FAILED;
 * the first step is h_init = 0.1 A; later line searches start from the last
-  accepted step (section 5.2), and from h_init again after a restart;
-* CG uses the usual positive PRP beta = <g+, g+ - g>/|g|^2 (section 4 prints
-  the beta formulas with a leading minus sign) and restarts from -g every
+  accepted step length |h| (section 5.2), and from h_init after a restart;
+* LS_PAR with G0 = false starts from the symmetric trials -h0/2, +h0/2 and
+  may return a negative step; the LS_H fallback then starts from the
+  smallest positive trial step;
+* CG uses the usual positive PRP beta = <g+, g+ - g>/|g|^2 by default
+  (section 4 prints the beta formulas with a leading minus sign; the other
+  variants named in section 5.1 are in ``cg_beta``) and restarts from -g every
   ``cg_restart`` iterations (default: the dimension 3N) and whenever its
   direction is not a descent direction;
+* optional FGM variant (off by default): the adaptive restart of O'Donoghue
+  and Candes 2015 sets theta back to 1 whenever an iterate has a higher
+  energy than the one before it;
 * stop when |grad|_inf < tol at the current point (FGM: at its best point),
   or after max_iter iterations.
 """
@@ -47,6 +54,8 @@ import numpy as np
 
 GD, FGM, CG, LBFGS = 0, 1, 2, 3
 LS_PAR, LS_H = 0, 1
+# CG beta variants named in section 5.1 (formulas as collected by Andrei 2008)
+CG_PRP, CG_FR, CG_HS, CG_PRP_PLUS, CG_CD, CG_LS, CG_DY = 0, 1, 2, 3, 4, 5, 6
 CONVERGED, MAX_ITER, LS_FAILED, NONFINITE_START = 0, 1, 2, 3
 EPS_MACH = float(np.finfo(np.float64).eps)
 
@@ -64,6 +73,9 @@ class MinParams:
     k_minus: float = 0.5
     eps_h: float = 1e-10
     cg_restart: int = 0         # 0: the dimension of x
+    cg_beta: int = CG_PRP
+    ls_par_g0: bool = True      # Algorithm 6's G0: use f and the slope at the base point
+    fgm_restart: bool = False   # restart FGM's momentum when f(x^{k+1}) > f(x^k)
 
     def primary_ls(self) -> int:
         if self.linesearch in (LS_PAR, LS_H):
@@ -108,9 +120,11 @@ def _parabola3_vertex(p0, p1, p2):
     return h if math.isfinite(h) else None
 
 
-def ls_par(fg, x, r, h0, f_star, s0, K=2, k_plus=2.0, k_minus=0.5):
-    """LS_PAR, Algorithm 6 with G0 = true (f* and the slope s0 = <grad f(x), r>
-    are known).  Returns (ok, h, f, g, smallest_trial_h)."""
+def ls_par(fg, x, r, h0, f_star, s0, K=2, k_plus=2.0, k_minus=0.5, g0=True):
+    """LS_PAR, Algorithm 6.  With g0 (G0 = true) the first parabola uses f* and
+    the slope s0 = <grad f(x), r>; without it the first two trials are the
+    symmetric steps -h0/2 and +h0/2.  Returns (ok, h, f, g, smallest positive
+    trial step or None)."""
     trials = []
 
     def probe(h):
@@ -118,25 +132,32 @@ def ls_par(fg, x, r, h0, f_star, s0, K=2, k_plus=2.0, k_minus=0.5):
         trials.append((h, f, g))
         return f
 
-    h1 = h0
-    f1 = probe(h1)
-    # parabola through (0, f*) with slope s0 and through (h1, f1)
-    if math.isfinite(f1):
-        a = (f1 - f_star - s0 * h1) / (h1 * h1)
-        if a > 0.0:
-            h2 = min(max(-s0 / (2.0 * a), 0.01 * h1), 10.0 * h1)
+    if g0:
+        h1 = h0
+        f1 = probe(h1)
+        # parabola through (0, f*) with slope s0 and through (h1, f1)
+        if math.isfinite(f1):
+            a = (f1 - f_star - s0 * h1) / (h1 * h1)
+            if a > 0.0:
+                h2 = min(max(-s0 / (2.0 * a), 0.01 * h1), 10.0 * h1)
+            else:
+                h2 = k_plus * h1
         else:
-            h2 = k_plus * h1
+            h2 = k_minus * h1
+        probe(h2)
     else:
-        h2 = k_minus * h1
-    probe(h2)
+        probe(-0.5 * h0)
+        probe(0.5 * h0)
     for _ in range(K - 2):
         pts = sorted([(0.0, f_star)] + [(h, f) for h, f, _ in trials], key=lambda p: _rank(p[1], p[0]))
         h3 = _parabola3_vertex(pts[0], pts[1], pts[2])
-        if h3 is None or h3 <= 0.0:
+        # with G0 the search runs along the descent direction only (h > 0);
+        # the symmetric start of G0 = false may also step backwards
+        if h3 is None or h3 == 0.0 or (g0 and h3 < 0.0):
             h3 = 0.5 * (pts[0][0] + pts[1][0])
         probe(h3)
-    h_min = min(h for h, _, _ in trials)
+    pos = [h for h, _, _ in trials if h > 0.0]
+    h_min = min(pos) if pos else None
     h, f, g = min(trials, key=lambda t: _rank(t[1], t[0]))
     if f < f_star:
         return True, h, f, g, h_min
@@ -167,8 +188,8 @@ def _search(fg, x, r, h0, f_star, s0, p: MinParams):
     trial step if the primary LS_PAR fails."""
     if p.primary_ls() == LS_H:
         return ls_h(fg, x, r, h0, f_star, p.k_plus, p.k_minus, p.eps_h)
-    ok, h, f, g, h_min = ls_par(fg, x, r, h0, f_star, s0, p.ls_K, p.k_plus, p.k_minus)
-    if ok:
+    ok, h, f, g, h_min = ls_par(fg, x, r, h0, f_star, s0, p.ls_K, p.k_plus, p.k_minus, p.ls_par_g0)
+    if ok or h_min is None:
         return ok, h, f, g
     return ls_h(fg, x, r, h_min, f_star, p.k_plus, p.k_minus, p.eps_h)
 
@@ -191,6 +212,34 @@ def lbfgs_direction(g, hist):
         b = rho * float(np.dot(y, r))
         r = r + (a - b) * s
     return r
+
+
+def cg_beta(variant, g, g_new, r):
+    """beta_k of the CG variants of section 5.1 (g = g_k, g_new = g_{k+1},
+    r = d_k the previous unnormalized direction, y = g_new - g).  A zero or
+    non-finite denominator gives beta = 0 (a restart)."""
+    y = g_new - g
+    gg = float(np.dot(g, g))
+    if variant == CG_PRP:
+        num, den = float(np.dot(g_new, y)), gg
+    elif variant == CG_FR:
+        num, den = float(np.dot(g_new, g_new)), gg
+    elif variant == CG_HS:
+        num, den = float(np.dot(g_new, y)), float(np.dot(r, y))
+    elif variant == CG_PRP_PLUS:
+        num, den = max(0.0, float(np.dot(g_new, y))), gg
+    elif variant == CG_CD:
+        num, den = float(np.dot(g_new, g_new)), -float(np.dot(r, g))
+    elif variant == CG_LS:
+        num, den = float(np.dot(g_new, y)), -float(np.dot(r, g))
+    elif variant == CG_DY:
+        num, den = float(np.dot(g_new, g_new)), float(np.dot(r, y))
+    else:
+        raise ValueError(f"unknown CG variant {variant}")
+    if den == 0.0:
+        return 0.0
+    beta = num / den
+    return beta if math.isfinite(beta) else 0.0
 
 
 def _ginf(g) -> float:
@@ -245,7 +294,7 @@ def _gd_cg_lbfgs(fg, x, f, g, p: MinParams, res: MinResult):
                 if len(hist) > p.m:
                     hist.popleft()
         elif p.method == CG:
-            beta = float(np.dot(g_new, g_new - g)) / float(np.dot(g, g))   # Polak-Ribiere-Polyak
+            beta = cg_beta(p.cg_beta, g, g_new, r)
             if (k + 1) % restart_every == 0:
                 r = -g_new
                 steepest = True
@@ -253,7 +302,7 @@ def _gd_cg_lbfgs(fg, x, f, g, p: MinParams, res: MinResult):
                 r = -g_new + beta * r
                 steepest = False
         x, f, g = x_new, f_new, g_new
-        h_prev = h
+        h_prev = abs(h)
         k += 1
         res.trace.append((f, h, res.evals))
     res.x, res.f, res.g, res.iters = x, f, g, k
@@ -299,9 +348,13 @@ def _fgm(fg, x, f, g, p: MinParams, res: MinResult):
             res.term = LS_FAILED
             break
         x_new = w + h * r
+        f_old = f
         x_prev, x, f, g = x, x_new, f_new, g_new
         theta_prev = theta
-        h_prev = h
+        if p.fgm_restart and f_new > f_old:
+            theta_prev = 1.0                   # function-value restart: no momentum next
+
+        h_prev = abs(h)
         if f_new < best[1]:
             best = (x_new, f_new, g_new)
         k += 1

@@ -19,7 +19,10 @@ from ._native import (  # noqa: F401
     FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START,
     FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H, FF_MIN_RESUME, FF_MIN_NO_CERTIFY,
     FF_OK, FF_ERR_ARG, FF_ERR_HIP, FF_ERR_WORKSPACE, FF_ERR_UNSUPPORTED,
+    FF_CG_PRP, FF_CG_FR, FF_CG_HS, FF_CG_PRP_PLUS, FF_CG_CD, FF_CG_LS, FF_CG_DY,
 )
+CG_BETAS = {"prp": FF_CG_PRP, "fr": FF_CG_FR, "hs": FF_CG_HS, "prp+": FF_CG_PRP_PLUS, "cd": FF_CG_CD,
+            "ls": FF_CG_LS, "dy": FF_CG_DY}
 
 METHODS = {"gd": FF_GD, "fgm": FF_FGM, "cg": FF_CG, "lbfgs": FF_LBFGS}
 PRECISIONS = {"fp64": FF_FP64, "fp32": FF_FP32_ACC64}
@@ -121,8 +124,8 @@ class Context:
     def minimize(self, x: torch.Tensor, method: str | int = "lbfgs", m: int = 10, tol: float = 1e-3,
                  max_iter: int = 2000, precision: str | int = "fp64", linesearch: int = FF_LS_DEFAULT,
                  ls_K: int = 2, h_init: float = 0.1, k_plus: float = 2.0, k_minus: float = 0.5,
-                 eps_h: float = 1e-10, cg_restart: int = 0, resume: bool = False, certify: bool = True,
-                 stream=None) -> dict:
+                 eps_h: float = 1e-10, cg_restart: int = 0, cg_beta: str | int = "prp", ls_par_g0: bool = True,
+                 fgm_restart: bool = False, resume: bool = False, certify: bool = True, stream=None) -> dict:
         """Minimize in place (x is overwritten with the result point); blocks."""
         x = self._coords(x)
         p = N.FFMinParams()
@@ -133,6 +136,9 @@ class Context:
         p.linesearch, p.ls_K = linesearch, ls_K
         p.h_init, p.k_plus, p.k_minus, p.eps_h = h_init, k_plus, k_minus, eps_h
         p.cg_restart = cg_restart
+        p.cg_beta = CG_BETAS.get(cg_beta, cg_beta)
+        p.ls_par_g0 = 1 if ls_par_g0 else 0
+        p.fgm_restart = 1 if fgm_restart else 0
         p.flags = (FF_MIN_RESUME if resume else 0) | (0 if certify else FF_MIN_NO_CERTIFY)
         r = N.FFMinResult()
         _check(N.load().ff_minimize(self._ctx, C.c_void_p(x.data_ptr()), C.byref(p), C.byref(r),

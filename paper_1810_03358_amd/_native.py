@@ -13,6 +13,7 @@ FF_FP64, FF_FP32_ACC64 = 0, 1
 FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START = 0, 1, 2, 3
 FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H = -1, 0, 1
 FF_MIN_RESUME, FF_MIN_NO_CERTIFY = 1, 2
+FF_CG_PRP, FF_CG_FR, FF_CG_HS, FF_CG_PRP_PLUS, FF_CG_CD, FF_CG_LS, FF_CG_DY = 0, 1, 2, 3, 4, 5, 6
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -33,7 +34,8 @@ class FFMinParams(C.Structure):
         ("method", C.c_int32), ("m", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
         ("precision", C.c_int32), ("linesearch", C.c_int32), ("ls_K", C.c_int32),
         ("h_init", C.c_double), ("k_plus", C.c_double), ("k_minus", C.c_double), ("eps_h", C.c_double),
-        ("cg_restart", C.c_int32), ("flags", C.c_int32),
+        ("cg_restart", C.c_int32), ("flags", C.c_int32), ("cg_beta", C.c_int32), ("ls_par_g0", C.c_int32),
+        ("fgm_restart", C.c_int32),
     ]
 
 

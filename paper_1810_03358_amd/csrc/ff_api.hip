@@ -165,6 +165,9 @@ void ff_default_params(ff_min_params* p) {
     p->eps_h = 1e-10;
     p->cg_restart = 0;
     p->flags = 0;
+    p->cg_beta = FF_CG_PRP;
+    p->ls_par_g0 = 1;
+    p->fgm_restart = 0;
 }
 
 const char* ff_last_error(void) { return g_err.c_str(); }
@@ -405,6 +408,9 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     if (!(p->h_init > 0.0) || !(p->k_plus > 1.0) || !(p->k_minus > 0.0 && p->k_minus < 1.0) || !(p->eps_h > 0.0))
         return fail(FF_ERR_ARG, "bad line-search constants");
     if (p->cg_restart < 0) return fail(FF_ERR_ARG, "cg_restart must be >= 0");
+    if (p->cg_beta < FF_CG_PRP || p->cg_beta > FF_CG_DY) return fail(FF_ERR_ARG, "bad cg_beta %d", p->cg_beta);
+    if (p->ls_par_g0 != 0 && p->ls_par_g0 != 1) return fail(FF_ERR_ARG, "ls_par_g0 must be 0 or 1");
+    if (p->fgm_restart != 0 && p->fgm_restart != 1) return fail(FF_ERR_ARG, "fgm_restart must be 0 or 1");
     const bool resume = (p->flags & FF_MIN_RESUME) != 0;
     if (resume && (c->last_method != p->method || c->last_m != p->m || c->last_prec != p->precision))
         return fail(FF_ERR_ARG, "resume needs the same method, m and precision as the previous call");
@@ -424,6 +430,9 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     d.ls_K = p->ls_K;
     d.cg_restart = p->cg_restart > 0 ? p->cg_restart : 3 * L.n;
     d.certify = (p->flags & FF_MIN_NO_CERTIFY) ? 0 : 1;
+    d.cg_beta = p->cg_beta;
+    d.ls_g0 = p->ls_par_g0;
+    d.fgm_restart = p->fgm_restart;
     d.tol = p->tol;
     d.h_init = p->h_init;
     d.k_plus = p->k_plus;

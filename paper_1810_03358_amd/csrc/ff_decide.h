@@ -27,8 +27,11 @@
 //    then CG and L-BFGS restart once from -g, FGM restarts its momentum once;
 //  - h starts at h_init and then at the last accepted step, h_init again
 //    after a restart;
-//  - CG: beta = <g+, g+ - g>/|g|^2, restart every cg_restart iterations and
-//    whenever the direction is not a descent direction;
+//  - CG: beta = <g+, g+ - g>/|g|^2 by default (or another variant named in
+//    section 5.1), restart every cg_restart iterations and whenever the
+//    direction is not a descent direction;
+//  - LS_PAR without G0 starts from -h0/2, +h0/2 and may step backwards; the
+//    next search starts from |h|;
 //  - stop when |g|_inf < tol at the current point (FGM: the best point) or
 //    after max_iter iterations.
 // In FF_FP32_ACC64 mode the run switches to FP64 evaluations once both line
@@ -121,7 +124,8 @@ __device__ inline void ls_start(Ctl* c, int base, double h0, int kind, bool firs
     c->ls_ntrials = 0;
     c->ls_hmin = __builtin_inf();
     c->ls_hstage = LSH_F0;
-    ls_trial(c, h0, first);
+    // LS_PAR without G0 starts from the symmetric trials -h0/2, +h0/2
+    ls_trial(c, (kind == LSK_PAR && !c->p.ls_g0) ? -0.5 * h0 : h0, first);
 }
 
 __device__ void ls_success(Ctl* c, int slot, double h);
@@ -149,10 +153,14 @@ __device__ inline void ls_after_trial(Ctl* c) {
         c->ls_th[n] = h;
         c->ls_tf[n] = f;
         c->ls_ntrials = n + 1;
-        c->ls_hmin = fmin(c->ls_hmin, h);
+        if (h > 0.0) c->ls_hmin = fmin(c->ls_hmin, h);
         if (c->ls_best < 0 || rank_less(f, h, c->e[c->ls_best], c->ls_th[kMaxLsTrials])) {
             c->ls_best = t;
             c->ls_th[kMaxLsTrials] = h;       // step of the best trial
+        }
+        if (c->ls_ntrials == 1 && !c->p.ls_g0) {
+            ls_trial(c, 0.5 * c->ls_h0, false);
+            return;
         }
         if (c->ls_ntrials == 1) {
             const double s0 = c->slope, fs = c->ls_fstar;
@@ -189,14 +197,15 @@ __device__ inline void ls_after_trial(Ctl* c) {
             }
             bool ok;
             double h3 = parabola3_vertex(bh[0], bf[0], bh[1], bf[1], bh[2], bf[2], ok);
-            if (!ok || h3 <= 0.0) h3 = 0.5 * (bh[0] + bh[1]);
+            // with G0 the search runs along the descent direction only (h > 0)
+            if (!ok || h3 == 0.0 || (c->p.ls_g0 && h3 < 0.0)) h3 = 0.5 * (bh[0] + bh[1]);
             ls_trial(c, h3, false);
             return;
         }
         const int b = c->ls_best;
         if (c->e[b] < c->ls_fstar) {
             ls_success(c, b, c->ls_th[kMaxLsTrials]);
-        } else if (!c->ls_fallback_done) {
+        } else if (!c->ls_fallback_done && isfinite(c->ls_hmin)) {
             // LS_H from the smallest trial step, same base and direction
             c->ls_fallback_done = 1;
             const double h0 = c->ls_hmin;
@@ -386,7 +395,7 @@ __device__ inline void fgm_after_momentum(Ctl* c) {
 }
 
 __device__ void ls_success(Ctl* c, int slot, double h) {
-    c->h_prev = h;
+    c->h_prev = fabs(h);
     c->accept_h = h;
     c->accept = 1;
     c->acc_new = slot;
@@ -418,6 +427,26 @@ __device__ void ls_failed(Ctl* c) {
     finish(c, T_LS_FAILED);
 }
 
+// beta of the CG variants (section 5.1) from |g|^2, |g+|^2, <g+,g>, <g+,d>,
+// <d,g>; y = g+ - g.  A zero or non-finite denominator gives 0 (a restart).
+__device__ inline double cg_beta(int variant, double gg, double gngn, double gng, double gnd, double dg) {
+    const double gny = gngn - gng;        // <g+, y>
+    const double dy = gnd - dg;           // <d, y>
+    double num, den;
+    switch (variant) {
+    case 1: num = gngn; den = gg; break;                    // FR
+    case 2: num = gny; den = dy; break;                     // HS
+    case 3: num = fmax(0.0, gny); den = gg; break;          // PRP+
+    case 4: num = gngn; den = -dg; break;                   // CD
+    case 5: num = gny; den = -dg; break;                    // LS
+    case 6: num = gngn; den = dy; break;                    // DY
+    default: num = gny; den = gg; break;                    // PRP
+    }
+    if (den == 0.0) return 0.0;
+    const double b = num / den;
+    return isfinite(b) ? b : 0.0;
+}
+
 // After the accept pass: update the method state and start the next iteration.
 __device__ inline void after_accept(Ctl* c, const double* dots) {
     const MinParamsDev& p = c->p;
@@ -427,8 +456,8 @@ __device__ inline void after_accept(Ctl* c, const double* dots) {
         c->cur = nw;
         break;
     case M_CG: {
-        // dots: [0] <g_new, g_old>, [1] <g_new, r_old>
-        const double beta = (c->g2[nw] - dots[0]) / c->g2[old];
+        // dots: [0] <g_new, g_old>, [1] <g_new, r_old>, [2] <r_old, g_old>
+        const double beta = cg_beta(p.cg_beta, c->g2[old], c->g2[nw], dots[0], dots[1], dots[2]);
         const int restart_every = p.cg_restart;
         if ((c->iters + 1) % restart_every == 0) {
             c->steepest = 1;
@@ -504,12 +533,16 @@ __device__ inline void after_accept(Ctl* c, const double* dots) {
         c->cur = nw;
         break;
     }
-    case M_FGM:
+    case M_FGM: {
+        const double f_old = c->e[c->cur];
         c->prev_x = c->cur;
         c->cur = nw;
         c->theta_prev = c->fgm_theta;
+        // optional function-value restart: no momentum after an uphill step
+        if (p.fgm_restart && c->e[nw] > f_old) c->theta_prev = 1.0;
         if (c->e[nw] < c->e[c->best]) c->best = nw;
         break;
+    }
     }
     const int ti = c->iters - c->iters_base;
     if (c->trace_ptr && ti < c->trace_cap) {

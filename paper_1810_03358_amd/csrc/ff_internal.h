@@ -59,7 +59,7 @@ enum LsKind : int32_t { LSK_PAR = 0, LSK_H = 1 };
 enum LsHStage : int32_t { LSH_F0 = 0, LSH_F1 = 1, LSH_SHRINK = 2 };
 
 struct MinParamsDev {
-    int32_t method, m, max_iter, precision, linesearch, ls_K, cg_restart, certify;
+    int32_t method, m, max_iter, precision, linesearch, ls_K, cg_restart, certify, cg_beta, ls_g0, fgm_restart;
     double tol, h_init, k_plus, k_minus, eps_h;
 };
 

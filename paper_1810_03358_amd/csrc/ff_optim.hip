@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
 
 // -------------------------------------------------------------------- accept
 // After a successful line search: method-specific vectors and dot products.
-//  CG:     <g_new, g_old>, <g_new, r_old>
+//  CG:     <g_new, g_old>, <g_new, r_old>, <r_old, g_old>
 //  L-BFGS: s = x_new - x_old and y = g_new - g_old (written to the spare
 //          history vectors), <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for
 //          every stored pair i, <s,S_i> <s,Y_i> <y,S_i> <y,Y_i> <g,S_i> <g,Y_i>.
@@ -234,6 +234,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
             for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 v[0] += gn[i] * go[i];
                 v[1] += gn[i] * r[i];
+                v[2] += r[i] * go[i];
             }
         } else if (row == 0) {
             double* ss = vec(a, c->spare_s);
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
     if (!is_last) return;
     __threadfence();
     __shared__ double dots[kMaxDots];
-    const int nd = method == M_LBFGS ? 6 * (nh + 1) : (method == M_CG ? 2 : 0);
+    const int nd = method == M_LBFGS ? 6 * (nh + 1) : (method == M_CG ? 3 : 0);
     for (int k = threadIdx.x; k < nd; k += kFinBlock) {
         const int r = k / 6, q = k - 6 * r;
         double acc = 0.0;

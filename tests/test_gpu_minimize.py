@@ -96,6 +96,34 @@ def test_fp64_ls_h_for_lbfgs_and_ls_par_for_fgm():
         compare_traces(tr, ref, 30)
 
 
+@pytest.mark.parametrize("beta", ["fr", "hs", "prp+", "cd", "ls", "dy"])
+def test_fp64_cg_variants(beta):
+    s = chain_system(300, 23)
+    code = {"fr": oracle.CG_FR, "hs": oracle.CG_HS, "prp+": oracle.CG_PRP_PLUS, "cd": oracle.CG_CD,
+            "ls": oracle.CG_LS, "dy": oracle.CG_DY}[beta]
+    ref = oracle_run(s, "cg", max_iter=30, cg_beta=code)
+    r, x, tr, _ = gpu_run(s, "cg", max_iter=30, cg_beta=beta)
+    assert r["term"] == ref.term and r["evals"] == ref.evals
+    compare_traces(tr, ref, 30)
+
+
+def test_fp64_fgm_with_restart():
+    s = config_system("chain512")
+    ref = oracle_run(s, "fgm", max_iter=40, fgm_restart=True)
+    r, x, tr, _ = gpu_run(s, "fgm", max_iter=40, fgm_restart=True)
+    assert r["term"] == ref.term and r["evals"] == ref.evals
+    compare_traces(tr, ref, 40)
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_fp64_ls_par_without_g0(K):
+    s = chain_system(260, 24)
+    ref = oracle_run(s, "lbfgs", max_iter=25, ls_K=K, ls_par_g0=False)
+    r, x, tr, _ = gpu_run(s, "lbfgs", max_iter=25, ls_K=K, ls_par_g0=False)
+    assert r["term"] == ref.term and r["evals"] == ref.evals
+    compare_traces(tr, ref, 25)
+
+
 def test_two_atom_lj_converges_to_the_closed_form_minimum():
     sig, eps = 3.3, 0.2
     s = make_system([[0, 0, 0], [1.5 * sig, 0.0, 0.0]], sigma=[sig, sig], eps=[eps, eps])

@@ -193,6 +193,18 @@ def test_fgm_best_point_is_monotone():
     assert res.f - fmin < 0.1 * (0.0 - fmin)
 
 
+def test_fgm_with_restart_converges_on_a_quadratic():
+    """With the function-value restart the accelerated method converges
+    linearly on a strictly convex quadratic (O'Donoghue and Candes 2015)."""
+    n = 40
+    A, b = _spd(n, 3, 1.0, 100.0)
+    fg = quad(A, b)
+    res = minimize(fg, np.zeros(n), MinParams(method=oracle.FGM, tol=1e-6, max_iter=3000, h_init=1.0,
+                                              fgm_restart=True))
+    assert res.term == oracle.CONVERGED and res.iters < 1000
+    assert np.abs(res.x - np.linalg.solve(A, b)).max() < 1e-5
+
+
 def test_fgm_isotropic_quadratic_one_step():
     lam = np.full(5, 2.0)
     b = np.arange(1.0, 6.0)
@@ -248,3 +260,48 @@ def test_chain512_lbfgs_descends():
     assert e0 > 1e10 and res.f < 0
     assert np.abs(res.g).max() < 1e-6 * np.abs(g0).max()
     assert res.evals == 1 + 2 * 200          # LS_PAR: two oracle calls per iteration
+
+
+# ------------------------------------------------------- CG variants, G0=false
+
+@pytest.mark.parametrize("variant", [oracle.CG_FR, oracle.CG_HS, oracle.CG_PRP_PLUS, oracle.CG_CD,
+                                     oracle.CG_LS, oracle.CG_DY])
+def test_cg_variants_coincide_on_a_quadratic(variant):
+    """With exact line searches on a strictly convex quadratic the gradients
+    are mutually orthogonal and orthogonal to the previous direction, so every
+    beta formula of section 5.1 reduces to the same value: the iterates of all
+    variants coincide with PRP's."""
+    n = 30
+    A, b = _spd(n, 4)
+    fg = quad(A, b)
+    ref = minimize(fg, np.zeros(n), MinParams(method=oracle.CG, tol=1e-14, max_iter=8, cg_restart=1000, h_init=1.0))
+    res = minimize(fg, np.zeros(n), MinParams(method=oracle.CG, tol=1e-14, max_iter=8, cg_restart=1000, h_init=1.0,
+                                              cg_beta=variant))
+    for (f1, h1, _), (f2, h2, _) in zip(ref.trace, res.trace):
+        assert f2 == pytest.approx(f1, rel=1e-11)
+        assert h2 == pytest.approx(h1, rel=1e-7)
+
+
+def test_cg_beta_values_on_orthogonal_gradients():
+    g = np.array([1.0, 0.0, 0.0])
+    gn = np.array([0.0, 2.0, 0.0])
+    r = -g
+    # <gn, g> = 0 and <r, gn> = 0: all variants give |gn|^2 / |g|^2 = 4
+    for v in (oracle.CG_PRP, oracle.CG_FR, oracle.CG_HS, oracle.CG_PRP_PLUS, oracle.CG_CD, oracle.CG_LS,
+              oracle.CG_DY):
+        assert oracle.cg_beta(v, g, gn, r) == pytest.approx(4.0, rel=1e-15)
+    # a zero denominator restarts
+    assert oracle.cg_beta(oracle.CG_HS, g, g, r) == 0.0
+
+
+def test_ls_par_without_g0_is_exact_on_a_parabola():
+    a, b, c = 2.0, -3.0, 0.5
+    probes = []
+
+    def fg(x):
+        probes.append(float(x[0]))
+        return a * x[0] ** 2 + b * x[0] + c, np.array([2 * a * x[0] + b])
+
+    ok, h, f, _, hmin = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, c, 0.0, K=3, g0=False)
+    assert probes[:2] == [-0.5, 0.5] and len(probes) == 3
+    assert ok and h == pytest.approx(-b / (2 * a), rel=1e-12) and hmin == 0.5
