@@ -141,34 +141,47 @@ typedef struct {
 
 typedef struct ff_ctx ff_ctx;   /* opaque host object bound to one workspace */
 
+/* A context holds a batch of n_sys >= 1 independent systems.  Their
+ * coordinates and gradients are passed concatenated: [sum of n_atoms][3] FP64,
+ * system 0 first.  Energies and results are per system.  Every system of a
+ * batch is minimized at the same time (the paper minimizes many docking poses
+ * independently, section 5.3); each one stops on its own criterion. */
+
 /* Bytes of device workspace a system needs; m_max is the largest L-BFGS
  * memory ff_minimize will be asked for (0 if only ff_energy_grad is used).
  * Returns 0 on invalid input. */
 size_t ff_workspace_bytes(const ff_system *sys, int32_t m_max);
+size_t ff_workspace_bytes_batch(const ff_system *systems, int32_t n_sys, int32_t m_max);
 
-/* Validate the system (indices in range, sizes, exclusion window), pack its
+/* Validate the system(s) (indices in range, sizes, exclusion window), pack
  * parameters and topology into the workspace and return a context.  Blocks
- * until the upload on `stream` is done. */
+ * until the upload on `stream` is done.  ff_create is a batch of one. */
 ff_status ff_create(const ff_system *sys, void *workspace, size_t workspace_bytes,
                     int32_t m_max, void *stream, ff_ctx **out);
+ff_status ff_create_batch(const ff_system *systems, int32_t n_sys, void *workspace,
+                          size_t workspace_bytes, int32_t m_max, void *stream, ff_ctx **out);
+
+/* Number of systems in the context. */
+int32_t ff_batch_size(const ff_ctx *ctx);
 
 /* Release the host context (the workspace stays the caller's). */
 ff_status ff_destroy(ff_ctx *ctx);
 
-/* E(x) and grad E(x) of section 2 at xyz (device, [n_atoms][3]).  energy:
- * device pointer to one double; grad: device [n_atoms][3] or NULL.  Enqueued
- * on `stream`, returns without waiting.  A clash gives IEEE inf/NaN values,
- * not an error. */
+/* E(x) and grad E(x) of section 2 at xyz (device, concatenated [n][3]).
+ * energy: device pointer to n_sys doubles; grad: device [n][3] or NULL.
+ * Enqueued on `stream`, returns without waiting.  A clash gives IEEE inf/NaN
+ * values, not an error. */
 ff_status ff_energy_grad(ff_ctx *ctx, const double *xyz, double *energy, double *grad,
                          int32_t precision, void *stream);
 
-/* Local minimization from xyz_inout (device, [n_atoms][3]); on return it
- * holds the result point: the last iterate for GD, CG and L-BFGS, the best
- * iterate for FGM (Algorithm 1).  Blocks until done. */
+/* Local minimization from xyz_inout (device, concatenated [n][3]); on return
+ * it holds the result points: the last iterate for GD, CG and L-BFGS, the best
+ * iterate for FGM (Algorithm 1).  result: host array of n_sys entries.
+ * Blocks until every system has stopped. */
 ff_status ff_minimize(ff_ctx *ctx, double *xyz_inout, const ff_min_params *params,
                       ff_min_result *result, void *stream);
 
-/* Per-iteration trace of the last ff_minimize on this context, for
+/* Per-iteration trace of system 0 in the last ff_minimize on this context, for
  * diagnostics and tests: host_out[3k .. 3k+2] = (E after iteration k, the
  * accepted step h, evaluations done so far), up to max_entries (the library
  * keeps the first 4096 iterations of a call).  Returns the number of entries

@@ -72,22 +72,31 @@ def _stream_ptr(stream=None):
 
 
 class Context:
-    """A prepared system on one GPU: workspace (torch uint8 tensor) + ff_ctx."""
+    """Prepared system(s) on one GPU: workspace (torch uint8 tensor) + ff_ctx.
 
-    def __init__(self, system: dict, m_max: int = 10, device="cuda", stream=None):
+    ``system`` is one system dict or a list of them (a batch, minimized
+    together; coordinates are then concatenated in list order)."""
+
+    def __init__(self, system, m_max: int = 10, device="cuda", stream=None):
         lib = N.load()
-        self.host = HostSystem(system)
-        self.n = self.host.n
+        self.is_batch = isinstance(system, (list, tuple))
+        systems = list(system) if self.is_batch else [system]
+        self.hosts = [HostSystem(d) for d in systems]
+        self.host = self.hosts[0]
+        self.n_sys = len(self.hosts)
+        self.sizes = [h.n for h in self.hosts]
+        self.n = sum(self.sizes)
         self.device = torch.device(device)
-        nbytes = int(lib.ff_workspace_bytes(C.byref(self.host.c), m_max))
+        self._sys_array = (N.FFSystem * self.n_sys)(*[h.c for h in self.hosts])
+        nbytes = int(lib.ff_workspace_bytes_batch(self._sys_array, self.n_sys, m_max))
         if nbytes == 0:
-            raise FFError(FF_ERR_ARG, "ff_workspace_bytes")
+            raise FFError(FF_ERR_ARG, "ff_workspace_bytes_batch")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         ctx = C.c_void_p()
-        _check(lib.ff_create(C.byref(self.host.c), C.c_void_p(self._ws_ptr), nbytes, m_max,
-                             _stream_ptr(stream), C.byref(ctx)), "ff_create")
+        _check(lib.ff_create_batch(self._sys_array, self.n_sys, C.c_void_p(self._ws_ptr), nbytes, m_max,
+                                   _stream_ptr(stream), C.byref(ctx)), "ff_create_batch")
         self._ctx = ctx
         self.m_max = m_max
 
@@ -114,7 +123,7 @@ class Context:
         on the current stream; returns device tensors."""
         x = self._coords(x)
         prec = PRECISIONS.get(precision, precision)
-        e = out_e if out_e is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+        e = out_e if out_e is not None else torch.empty(self.n_sys, dtype=torch.float64, device=x.device)
         g = (out_g if out_g is not None else torch.empty_like(x)) if want_grad else None
         _check(N.load().ff_energy_grad(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(e.data_ptr()),
                                        C.c_void_p(g.data_ptr()) if g is not None else None, int(prec),
@@ -126,7 +135,8 @@ class Context:
                  ls_K: int = 2, h_init: float = 0.1, k_plus: float = 2.0, k_minus: float = 0.5,
                  eps_h: float = 1e-10, cg_restart: int = 0, cg_beta: str | int = "prp", ls_par_g0: bool = True,
                  fgm_restart: bool = False, resume: bool = False, certify: bool = True, stream=None) -> dict:
-        """Minimize in place (x is overwritten with the result point); blocks."""
+        """Minimize in place (x is overwritten with the result point(s)); blocks.
+        Returns a result dict (a list of them for a batch)."""
         x = self._coords(x)
         p = N.FFMinParams()
         N.load().ff_default_params(C.byref(p))
@@ -140,11 +150,12 @@ class Context:
         p.ls_par_g0 = 1 if ls_par_g0 else 0
         p.fgm_restart = 1 if fgm_restart else 0
         p.flags = (FF_MIN_RESUME if resume else 0) | (0 if certify else FF_MIN_NO_CERTIFY)
-        r = N.FFMinResult()
-        _check(N.load().ff_minimize(self._ctx, C.c_void_p(x.data_ptr()), C.byref(p), C.byref(r),
+        res = (N.FFMinResult * self.n_sys)()
+        _check(N.load().ff_minimize(self._ctx, C.c_void_p(x.data_ptr()), C.byref(p), res,
                                     _stream_ptr(stream)), "ff_minimize")
-        return dict(term=r.term, term_name=TERMS.get(r.term, str(r.term)), iters=r.iters, evals=r.evals,
-                    evals_fp64=r.evals_fp64, energy=r.energy, grad_inf=r.grad_inf, grad_2=r.grad_2)
+        out = [dict(term=r.term, term_name=TERMS.get(r.term, str(r.term)), iters=r.iters, evals=r.evals,
+                    evals_fp64=r.evals_fp64, energy=r.energy, grad_inf=r.grad_inf, grad_2=r.grad_2) for r in res]
+        return out if self.is_batch else out[0]
 
     def time_pair(self, x: torch.Tensor, precision: str | int = "fp32", reps: int = 20, stream=None) -> float:
         """Average duration (ms) of the pair kernel alone at x, HIP-event timed."""

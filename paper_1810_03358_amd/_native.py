@@ -46,8 +46,9 @@ class FFMinResult(C.Structure):
     ]
 
 
-EXPORTS = ("ff_workspace_bytes", "ff_create", "ff_destroy", "ff_energy_grad", "ff_minimize",
-           "ff_get_trace", "ff_time_pair", "ff_default_params", "ff_last_error")
+EXPORTS = ("ff_workspace_bytes", "ff_workspace_bytes_batch", "ff_create", "ff_create_batch", "ff_batch_size",
+           "ff_destroy", "ff_energy_grad", "ff_minimize", "ff_get_trace", "ff_time_pair", "ff_default_params",
+           "ff_last_error")
 
 _lib = None
 
@@ -65,6 +66,13 @@ def load():
     lib.ff_create.argtypes = [C.POINTER(FFSystem), C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
                               C.POINTER(C.c_void_p)]
     lib.ff_create.restype = C.c_int
+    lib.ff_workspace_bytes_batch.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_int32]
+    lib.ff_workspace_bytes_batch.restype = C.c_size_t
+    lib.ff_create_batch.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_void_p, C.c_size_t, C.c_int32,
+                                    C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.ff_create_batch.restype = C.c_int
+    lib.ff_batch_size.argtypes = [C.c_void_p]
+    lib.ff_batch_size.restype = C.c_int32
     lib.ff_destroy.argtypes = [C.c_void_p]
     lib.ff_destroy.restype = C.c_int
     lib.ff_energy_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]

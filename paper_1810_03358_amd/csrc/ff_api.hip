@@ -2,13 +2,14 @@
 // workspace layout, one-time packing of parameters and topology, and the
 // launch sequence of an evaluation or a minimization.
 //
-// A minimization is a fixed cycle of six kernels captured once into a HIP
-// graph: build the point (trial / direction / momentum) -> bonded terms ->
-// FP32 pair kernel -> FP64 pair kernel -> finalize (+ decision) -> accept
-// pass (+ decision).  Only
-// one of the two pair kernels does work in a cycle; the others return at
-// once when the control block says they have nothing to do.  The host
-// replays the graph and polls one completion flag.
+// A context holds a batch of independent systems (one or more).  A
+// minimization is a fixed cycle of six kernels captured once into a HIP graph:
+// build the point (trial / direction / momentum) -> bonded terms -> FP32 pair
+// kernel -> FP64 pair kernel -> finalize (+ decision) -> accept pass (+
+// decision).  Each cycle advances every unfinished system by one evaluation;
+// work of a system that has nothing to do in a kernel returns at once (its
+// control block says so).  The host replays the graph and polls the number of
+// finished systems.
 #include <algorithm>
 #include <cstdarg>
 #include <cstddef>
@@ -37,8 +38,9 @@ using namespace ff;
 struct ff_ctx {
     Layout L;
     char* ws;
-    int32_t* host_flag;          // pinned: done flag polled by ff_minimize
-    Ctl* host_ctl;               // pinned copy of the control block
+    std::vector<SysInfo> sys;    // host copy of the per-system info
+    int32_t* host_flag;          // pinned: polled batch counters
+    Ctl* host_ctl;               // pinned copy of one control block
     hipGraphExec_t graph = nullptr;
     hipStream_t own = nullptr;   // private stream: graph capture, and calls made on the NULL stream
     int last_method = -1, last_m = -1, last_prec = -1;
@@ -65,17 +67,26 @@ static ff_status fail(ff_status st, const char* fmt, ...) {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ layout
-static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
+// Tile configuration: a single system picks its I-block by size; a batch of
+// several systems uses 64-atom I-blocks so that small systems are padded to a
+// multiple of 64 only.  "FF_PAIR_CONFIG=cfg[,chunk]" overrides (tuning).
+static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, std::vector<SysInfo>* out) {
     std::memset(&L, 0, sizeof L);
-    if (!s || s->n_atoms < 1 || s->n_bonds < 0 || s->n_angles < 0 || s->n_dihedrals < 0) return false;
+    if (!s || n_sys < 1) return false;
     if (m_max < 0 || m_max > kMaxM) return false;
-    L.n = s->n_atoms;
-    L.np = (L.n + kAtomAlign - 1) / kAtomAlign * kAtomAlign;
-    if (L.np <= 2048) { L.cfg = 0; L.chunk = 2; }
-    else if (L.np <= 16384) { L.cfg = 1; L.chunk = 4; }
+    long long n_tot = 0;
+    int n_max = 0;
+    for (int k = 0; k < n_sys; ++k) {
+        if (s[k].n_atoms < 1 || s[k].n_bonds < 0 || s[k].n_angles < 0 || s[k].n_dihedrals < 0) return false;
+        n_tot += s[k].n_atoms;
+        n_max = std::max(n_max, s[k].n_atoms);
+    }
+    if (n_tot > (1 << 28)) return false;
+    L.n_sys = n_sys;
+    if (n_sys > 1) { L.cfg = 0; L.chunk = 4; }
+    else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
+    else if (n_max <= 16384) { L.cfg = 1; L.chunk = 4; }
     else { L.cfg = 2; L.chunk = 8; }
-    // tuning override "cfg[,chunk]" (read when the workspace is sized and
-    // when it is created, so both agree)
     if (const char* env = std::getenv("FF_PAIR_CONFIG")) {
         int cfg = -1, chunk = 0;
         const int got = std::sscanf(env, "%d,%d", &cfg, &chunk);
@@ -83,30 +94,72 @@ static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
         if (got == 2 && chunk >= 1 && chunk <= 4096) L.chunk = chunk;
     }
     L.block = kTileConfigs[L.cfg].block;
-    L.nb = L.np / L.block;
-    L.nt = L.np / kTile;
-    L.n_units = 0;
-    L.n_chunks = 0;
-    for (int b = 0; b < L.nb; ++b) {
-        const int t0 = b * L.block / kTile;
-        const int units = L.nt - t0;
-        L.n_units += units;
-        L.n_chunks += (units + L.chunk - 1) / L.chunk;
+    std::vector<SysInfo> sys(n_sys);
+    int aoff = 0, uoff = 0, units = 0, chunks = 0, nbd = 0, nag = 0, ndh = 0, ebo = 0;
+    size_t red = 0;
+    L.accept_bx = std::max(1, std::min(64, (3 * n_max + 8 * kFinBlock - 1) / (8 * kFinBlock)));
+    for (int k = 0; k < n_sys; ++k) {
+        SysInfo& si = sys[k];
+        std::memset(&si, 0, sizeof si);
+        si.n = s[k].n_atoms;
+        si.np = (si.n + L.block - 1) / L.block * L.block;
+        si.aoff = aoff;
+        si.uoff = uoff;
+        si.row0 = aoff / L.block;
+        si.nb = si.np / L.block;
+        si.chunk0 = chunks;
+        const int nt = si.np / kTile;
+        for (int b = 0; b < si.nb; ++b) {
+            const int t0 = b * L.block / kTile;
+            units += nt - t0;
+            chunks += (nt - t0 + L.chunk - 1) / L.chunk;
+        }
+        si.n_chunks = chunks - si.chunk0;
+        si.n_bonds = s[k].n_bonds;
+        si.n_angles = s[k].n_angles;
+        si.n_dihedrals = s[k].n_dihedrals;
+        si.bond0 = nbd;
+        si.angle0 = nag;
+        si.dih0 = ndh;
+        nbd += si.n_bonds;
+        nag += si.n_angles;
+        ndh += si.n_dihedrals;
+        const int terms = si.n_bonds + si.n_angles + si.n_dihedrals;
+        si.bonded_blocks = std::max(1, (terms + kBondedPerBlock - 1) / kBondedPerBlock);
+        si.eb0 = ebo;
+        ebo += si.bonded_blocks;
+        si.fin_blocks = (si.n + kFinBlock - 1) / kFinBlock;
+        si.vec_blocks = (3 * si.n + kFinBlock - 1) / kFinBlock;
+        si.red0 = (int32_t)red;
+        red += std::max((size_t)si.fin_blocks * 3, (size_t)L.accept_bx * (kMaxM + 1) * 6);
+        L.max_fin_blocks = std::max(L.max_fin_blocks, si.fin_blocks);
+        L.max_vec_blocks = std::max(L.max_vec_blocks, si.vec_blocks);
+        L.max_bonded_blocks = std::max(L.max_bonded_blocks, si.bonded_blocks);
+        aoff += si.np;
+        uoff += si.n;
     }
-    L.n_bonds = s->n_bonds;
-    L.n_angles = s->n_angles;
-    L.n_dihedrals = s->n_dihedrals;
-    L.n_terms_slots = 2 * L.n_bonds + 3 * L.n_angles + 4 * L.n_dihedrals;
-    const int n_terms = L.n_bonds + L.n_angles + L.n_dihedrals;
-    L.n_bonded_blocks = std::max(1, (n_terms + kBondedPerBlock - 1) / kBondedPerBlock);
-    L.n_fin_blocks = (L.n + kFinBlock - 1) / kFinBlock;
-    L.accept_bx = std::max(1, std::min(64, (3 * L.n + 8 * kFinBlock - 1) / (8 * kFinBlock)));
+    L.n = uoff;
+    L.np = aoff;
+    L.nb = aoff / L.block;
+    L.nt = aoff / kTile;
+    L.n_units = units;
+    L.n_chunks = chunks;
+    L.n_bonds = nbd;
+    L.n_angles = nag;
+    L.n_dihedrals = ndh;
+    L.n_terms_slots = 2 * nbd + 3 * nag + 4 * ndh;
+    L.n_bonded_blocks = ebo;
+    L.n_fin_blocks = 0;
+    for (auto& si : sys) L.n_fin_blocks += si.fin_blocks;
     L.m_max = m_max;
     L.vstride = (3 * (size_t)L.np + 31) / 32 * 32;
+    L.ctl_stride = align256(sizeof(Ctl));
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
     const size_t np = L.np;
-    L.off_ctl = take(sizeof(Ctl));
+    L.off_batch = take(sizeof(BatchState));
+    L.off_sys = take((size_t)n_sys * sizeof(SysInfo));
+    L.off_ctl = take((size_t)n_sys * L.ctl_stride);
     L.off_c12 = take(np * 4);
     L.off_c6 = take(np * 4);
     L.off_q = take(np * 4);
@@ -129,11 +182,10 @@ static bool make_layout(const ff_system* s, int32_t m_max, Layout& L) {
     L.off_eb = take((size_t)L.n_bonded_blocks * 8);
     L.off_inc_start = take((np + 1) * 4);
     L.off_inc = take((size_t)L.n_terms_slots * 4);
-    const size_t vec_blocks = (3 * np + kFinBlock - 1) / kFinBlock;
-    L.off_red = take(std::max({vec_blocks * 3, (size_t)L.accept_bx * (kMaxM + 1) * 6,
-                               (size_t)L.n_fin_blocks * 3}) * 8);
+    L.off_red = take(red * 8);
     L.off_vec = take((size_t)V_COUNT * L.vstride * 8 + (size_t)kTraceCap * 3 * 8);
     L.total = o;
+    if (out) *out = std::move(sys);
     return true;
 }
 
@@ -141,14 +193,61 @@ static double* trace_buffer(const ff_ctx* c) {
     return at<double>(c->ws, c->L.off_vec) + (size_t)V_COUNT * c->L.vstride;
 }
 
+// Host-side validation of one system; returns FF_OK or the error.
+static ff_status validate_system(const ff_system* s, int k, std::vector<uint64_t>& excl, int aoff) {
+    const int n = s->n_atoms;
+    if (!s->q || !s->sigma || !s->eps) return fail(FF_ERR_ARG, "system %d: per-atom parameter arrays are null", k);
+    if ((s->n_bonds && (!s->bond || !s->bond_k || !s->bond_r0)) ||
+        (s->n_angles && (!s->angle || !s->angle_k || !s->angle_t0)) ||
+        (s->n_dihedrals && (!s->dihedral || !s->dihedral_v)))
+        return fail(FF_ERR_ARG, "system %d: topology arrays are null", k);
+    if (!(std::isfinite(s->coulomb_c))) return fail(FF_ERR_ARG, "system %d: coulomb_c is not finite", k);
+    if (s->coulomb_c < 0.0) return fail(FF_ERR_UNSUPPORTED, "system %d: negative coulomb_c", k);
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(s->q[i]) || !(s->sigma[i] >= 0.0) || !(s->eps[i] >= 0.0) || !std::isfinite(s->sigma[i]) ||
+            !std::isfinite(s->eps[i]))
+            return fail(FF_ERR_ARG, "system %d: bad parameters of atom %d (sigma, eps must be finite and >= 0)", k, i);
+    auto add_excl = [&](int i, int j) -> ff_status {
+        if (i == j) return fail(FF_ERR_ARG, "system %d: a bond or angle joins atom %d to itself", k, i);
+        const int lo = std::min(i, j), hi = std::max(i, j);
+        if (hi - lo > kExclWindow)
+            return fail(FF_ERR_UNSUPPORTED, "system %d: excluded pair (%d, %d) is more than %d atoms apart", k, lo, hi,
+                        kExclWindow);
+        excl[aoff + lo] |= 1ull << (hi - lo - 1);
+        return FF_OK;
+    };
+    for (int b = 0; b < s->n_bonds; ++b) {
+        const int i = s->bond[2 * b], j = s->bond[2 * b + 1];
+        if (i < 0 || i >= n || j < 0 || j >= n) return fail(FF_ERR_ARG, "system %d: bond %d has an atom index out of range", k, b);
+        if (!std::isfinite(s->bond_k[b]) || !std::isfinite(s->bond_r0[b])) return fail(FF_ERR_ARG, "system %d: bond %d parameters", k, b);
+        ff_status st = add_excl(i, j);
+        if (st) return st;
+    }
+    for (int a = 0; a < s->n_angles; ++a) {
+        const int* t = s->angle + 3 * a;
+        for (int q = 0; q < 3; ++q)
+            if (t[q] < 0 || t[q] >= n) return fail(FF_ERR_ARG, "system %d: angle %d has an atom index out of range", k, a);
+        if (t[0] == t[1] || t[1] == t[2]) return fail(FF_ERR_ARG, "system %d: angle %d repeats its vertex", k, a);
+        ff_status st = add_excl(t[0], t[2]);
+        if (st) return st;
+    }
+    for (int d = 0; d < s->n_dihedrals; ++d)
+        for (int q = 0; q < 4; ++q)
+            if (s->dihedral[4 * d + q] < 0 || s->dihedral[4 * d + q] >= n)
+                return fail(FF_ERR_ARG, "system %d: dihedral %d has an atom index out of range", k, d);
+    return FF_OK;
+}
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
-size_t ff_workspace_bytes(const ff_system* sys, int32_t m_max) {
+size_t ff_workspace_bytes_batch(const ff_system* sys, int32_t n_sys, int32_t m_max) {
     Layout L;
-    if (!make_layout(sys, m_max, L)) return 0;
+    if (!make_layout(sys, n_sys, m_max, L, nullptr)) return 0;
     return L.total;
 }
+
+size_t ff_workspace_bytes(const ff_system* sys, int32_t m_max) { return ff_workspace_bytes_batch(sys, 1, m_max); }
 
 void ff_default_params(ff_min_params* p) {
     if (!p) return;
@@ -172,115 +271,108 @@ void ff_default_params(ff_min_params* p) {
 
 const char* ff_last_error(void) { return g_err.c_str(); }
 
-ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_t m_max, void* stream,
-                    ff_ctx** out) {
+int32_t ff_batch_size(const ff_ctx* c) { return c ? c->L.n_sys : 0; }
+
+ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes, int32_t m_max,
+                          void* stream, ff_ctx** out) {
     g_err.clear();
     if (!out) return fail(FF_ERR_ARG, "out is null");
     *out = nullptr;
-    if (!s) return fail(FF_ERR_ARG, "system is null");
-    const int n = s->n_atoms;
-    if (n < 1) return fail(FF_ERR_ARG, "n_atoms must be >= 1");
-    if (!s->q || !s->sigma || !s->eps) return fail(FF_ERR_ARG, "per-atom parameter arrays are null");
-    if ((s->n_bonds && (!s->bond || !s->bond_k || !s->bond_r0)) ||
-        (s->n_angles && (!s->angle || !s->angle_k || !s->angle_t0)) ||
-        (s->n_dihedrals && (!s->dihedral || !s->dihedral_v)))
-        return fail(FF_ERR_ARG, "topology arrays are null");
+    if (!systems || n_sys < 1) return fail(FF_ERR_ARG, "need at least one system");
+    for (int k = 0; k < n_sys; ++k)
+        if (systems[k].n_atoms < 1) return fail(FF_ERR_ARG, "system %d: n_atoms must be >= 1", k);
     if (m_max < 0 || m_max > kMaxM) return fail(FF_ERR_ARG, "m_max must be in [0, %d]", kMaxM);
-    if (!(std::isfinite(s->coulomb_c))) return fail(FF_ERR_ARG, "coulomb_c is not finite");
-    if (s->coulomb_c < 0.0) return fail(FF_ERR_UNSUPPORTED, "negative coulomb_c");
     Layout L;
-    if (!make_layout(s, m_max, L)) return fail(FF_ERR_ARG, "invalid sizes");
+    std::vector<SysInfo> sys;
+    if (!make_layout(systems, n_sys, m_max, L, &sys)) return fail(FF_ERR_ARG, "invalid sizes");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(FF_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
     if (ws_bytes < L.total) return fail(FF_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
-    for (int i = 0; i < n; ++i)
-        if (!std::isfinite(s->q[i]) || !(s->sigma[i] >= 0.0) || !(s->eps[i] >= 0.0) || !std::isfinite(s->sigma[i]) ||
-            !std::isfinite(s->eps[i]))
-            return fail(FF_ERR_ARG, "bad parameters of atom %d (sigma, eps must be finite and >= 0)", i);
-    // exclusion bitmasks: bit d-1 of atom i marks the pair (i, i+d)
     std::vector<uint64_t> excl(L.np, 0ull);
-    auto add_excl = [&](int i, int j) -> ff_status {
-        if (i == j) return fail(FF_ERR_ARG, "a bond or angle joins atom %d to itself", i);
-        const int lo = std::min(i, j), hi = std::max(i, j);
-        if (hi - lo > kExclWindow)
-            return fail(FF_ERR_UNSUPPORTED, "excluded pair (%d, %d) is more than %d atoms apart", lo, hi, kExclWindow);
-        excl[lo] |= 1ull << (hi - lo - 1);
-        return FF_OK;
-    };
-    for (int b = 0; b < s->n_bonds; ++b) {
-        const int i = s->bond[2 * b], j = s->bond[2 * b + 1];
-        if (i < 0 || i >= n || j < 0 || j >= n) return fail(FF_ERR_ARG, "bond %d has an atom index out of range", b);
-        if (!std::isfinite(s->bond_k[b]) || !std::isfinite(s->bond_r0[b])) return fail(FF_ERR_ARG, "bond %d parameters", b);
-        ff_status st = add_excl(i, j);
+    for (int k = 0; k < n_sys; ++k) {
+        ff_status st = validate_system(&systems[k], k, excl, sys[k].aoff);
         if (st) return st;
     }
-    for (int a = 0; a < s->n_angles; ++a) {
-        const int* t = s->angle + 3 * a;
-        for (int k = 0; k < 3; ++k)
-            if (t[k] < 0 || t[k] >= n) return fail(FF_ERR_ARG, "angle %d has an atom index out of range", a);
-        if (t[0] == t[1] || t[1] == t[2]) return fail(FF_ERR_ARG, "angle %d repeats its vertex", a);
-        ff_status st = add_excl(t[0], t[2]);
-        if (st) return st;
-    }
-    for (int d = 0; d < s->n_dihedrals; ++d)
-        for (int k = 0; k < 4; ++k)
-            if (s->dihedral[4 * d + k] < 0 || s->dihedral[4 * d + k] >= n)
-                return fail(FF_ERR_ARG, "dihedral %d has an atom index out of range", d);
-
-    // per-atom factors: c12 = 2 sqrt(eps) sigma^6, c6 = 2 sqrt(eps) sigma^3, q^ = sqrt(C) q
-    const double sqc = std::sqrt(s->coulomb_c);
+    // per-atom factors: c12 = 2 sqrt(eps) sigma^6, c6 = 2 sqrt(eps) sigma^3, q^ = sqrt(C) q;
+    // padding atoms keep zero factors
     std::vector<float> c12f(L.np, 0.f), c6f(L.np, 0.f), qf(L.np, 0.f);
     std::vector<double> c12d(L.np, 0.0), c6d(L.np, 0.0), qd(L.np, 0.0);
-    for (int i = 0; i < n; ++i) {
-        const double se = 2.0 * std::sqrt(s->eps[i]);
-        const double s3 = s->sigma[i] * s->sigma[i] * s->sigma[i];
-        c12d[i] = se * s3 * s3;
-        c6d[i] = se * s3;
-        qd[i] = sqc * s->q[i];
-        c12f[i] = (float)c12d[i];
-        c6f[i] = (float)c6d[i];
-        qf[i] = (float)qd[i];
+    for (int k = 0; k < n_sys; ++k) {
+        const ff_system& s = systems[k];
+        const double sqc = std::sqrt(s.coulomb_c);
+        for (int i = 0; i < s.n_atoms; ++i) {
+            const int g = sys[k].aoff + i;
+            const double se = 2.0 * std::sqrt(s.eps[i]);
+            const double s3 = s.sigma[i] * s.sigma[i] * s.sigma[i];
+            c12d[g] = se * s3 * s3;
+            c6d[g] = se * s3;
+            qd[g] = sqc * s.q[i];
+            c12f[g] = (float)c12d[g];
+            c6f[g] = (float)c6d[g];
+            qf[g] = (float)qd[g];
+        }
     }
-    // tile tables
+    // tile tables (global I-block and j-tile indices)
     std::vector<ChunkInfo> chunks;
     std::vector<RowInfo> rows(L.nb);
     int unit = 0;
-    for (int b = 0; b < L.nb; ++b) {
-        const int t0 = b * L.block / kTile;
-        rows[b].unit_start = unit;
-        rows[b].t0 = t0;
-        rows[b].chunk_start = (int)chunks.size();
-        for (int t = t0; t < L.nt; t += L.chunk) {
-            ChunkInfo c;
-            c.row = b;
-            c.t_begin = t;
-            c.t_end = std::min(t + L.chunk, L.nt);
-            c.unit_base = unit + (t - t0);
-            chunks.push_back(c);
+    for (int k = 0; k < n_sys; ++k) {
+        const SysInfo& si = sys[k];
+        const int tile0 = si.aoff / kTile, nt = si.np / kTile;
+        for (int b = 0; b < si.nb; ++b) {
+            const int row = si.row0 + b;
+            const int t0 = tile0 + b * L.block / kTile, t_end = tile0 + nt;
+            rows[row].unit_start = unit;
+            rows[row].t0 = t0;
+            rows[row].chunk_start = (int)chunks.size();
+            for (int t = t0; t < t_end; t += L.chunk) {
+                ChunkInfo c{};
+                c.row = row;
+                c.t_begin = t;
+                c.t_end = std::min(t + L.chunk, t_end);
+                c.unit_base = unit + (t - t0);
+                c.sys = k;
+                chunks.push_back(c);
+            }
+            rows[row].n_chunks = (int)chunks.size() - rows[row].chunk_start;
+            unit += t_end - t0;
         }
-        rows[b].n_chunks = (int)chunks.size() - rows[b].chunk_start;
-        unit += L.nt - t0;
     }
-    // bonded topology and the incidence lists (term-slot indices per atom)
+    // bonded topology (local atom indices) and the incidence lists (global
+    // term-slot indices per global padded atom)
     std::vector<int> bond(2 * (size_t)L.n_bonds), angle(3 * (size_t)L.n_angles), dih(4 * (size_t)L.n_dihedrals);
     std::vector<double> bondp(2 * (size_t)L.n_bonds), anglep(2 * (size_t)L.n_angles), dihp(4 * (size_t)L.n_dihedrals);
     std::vector<std::vector<int>> inc_lists(L.np);
-    for (int b = 0; b < L.n_bonds; ++b) {
-        for (int k = 0; k < 2; ++k) { bond[2 * b + k] = s->bond[2 * b + k]; inc_lists[bond[2 * b + k]].push_back(2 * b + k); }
-        bondp[2 * b] = s->bond_k[b];
-        bondp[2 * b + 1] = s->bond_r0[b];
-    }
     const int abase = 2 * L.n_bonds, dbase = abase + 3 * L.n_angles;
-    for (int a = 0; a < L.n_angles; ++a) {
-        for (int k = 0; k < 3; ++k) { angle[3 * a + k] = s->angle[3 * a + k]; inc_lists[angle[3 * a + k]].push_back(abase + 3 * a + k); }
-        anglep[2 * a] = s->angle_k[a];
-        anglep[2 * a + 1] = s->angle_t0[a];
-    }
-    for (int d = 0; d < L.n_dihedrals; ++d)
-        for (int k = 0; k < 4; ++k) {
-            dih[4 * d + k] = s->dihedral[4 * d + k];
-            dihp[4 * d + k] = s->dihedral_v[4 * d + k];
-            inc_lists[dih[4 * d + k]].push_back(dbase + 4 * d + k);
+    for (int k = 0; k < n_sys; ++k) {
+        const ff_system& s = systems[k];
+        const SysInfo& si = sys[k];
+        for (int b = 0; b < s.n_bonds; ++b) {
+            const int gb = si.bond0 + b;
+            for (int q = 0; q < 2; ++q) {
+                bond[2 * gb + q] = s.bond[2 * b + q];
+                inc_lists[si.aoff + s.bond[2 * b + q]].push_back(2 * gb + q);
+            }
+            bondp[2 * gb] = s.bond_k[b];
+            bondp[2 * gb + 1] = s.bond_r0[b];
         }
+        for (int a = 0; a < s.n_angles; ++a) {
+            const int ga = si.angle0 + a;
+            for (int q = 0; q < 3; ++q) {
+                angle[3 * ga + q] = s.angle[3 * a + q];
+                inc_lists[si.aoff + s.angle[3 * a + q]].push_back(abase + 3 * ga + q);
+            }
+            anglep[2 * ga] = s.angle_k[a];
+            anglep[2 * ga + 1] = s.angle_t0[a];
+        }
+        for (int d = 0; d < s.n_dihedrals; ++d) {
+            const int gd = si.dih0 + d;
+            for (int q = 0; q < 4; ++q) {
+                dih[4 * gd + q] = s.dihedral[4 * d + q];
+                dihp[4 * gd + q] = s.dihedral_v[4 * d + q];
+                inc_lists[si.aoff + s.dihedral[4 * d + q]].push_back(dbase + 4 * gd + q);
+            }
+        }
+    }
     std::vector<int> inc_start(L.np + 1, 0), inc;
     inc.reserve(L.n_terms_slots);
     for (int i = 0; i < L.np; ++i) {
@@ -295,6 +387,7 @@ ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_
         if (!bytes) return hipSuccess;
         return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
     };
+    HIP_TRY(up(L.off_sys, sys.data(), sys.size() * sizeof(SysInfo)));
     HIP_TRY(up(L.off_c12, c12f.data(), c12f.size() * 4));
     HIP_TRY(up(L.off_c6, c6f.data(), c6f.size() * 4));
     HIP_TRY(up(L.off_q, qf.data(), qf.size() * 4));
@@ -321,6 +414,7 @@ ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_
     ff_ctx* c = new ff_ctx();
     c->L = L;
     c->ws = ws;
+    c->sys = std::move(sys);
     void* hf = nullptr;
     void* hc = nullptr;
     if (hipHostMalloc(&hf, 256, hipHostMallocDefault) != hipSuccess ||
@@ -339,6 +433,16 @@ ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_
     }
     *out = c;
     return FF_OK;
+}
+
+ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_t m_max, void* stream,
+                    ff_ctx** out) {
+    if (!s) {
+        g_err = "system is null";
+        if (out) *out = nullptr;
+        return FF_ERR_ARG;
+    }
+    return ff_create_batch(s, 1, workspace, ws_bytes, m_max, stream, out);
 }
 
 ff_status ff_destroy(ff_ctx* c) {
@@ -428,7 +532,7 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     d.precision = p->precision;
     d.linesearch = p->linesearch;
     d.ls_K = p->ls_K;
-    d.cg_restart = p->cg_restart > 0 ? p->cg_restart : 3 * L.n;
+    d.cg_restart = p->cg_restart;     // 0: 3N of each system (set per system on the device)
     d.certify = (p->flags & FF_MIN_NO_CERTIFY) ? 0 : 1;
     d.cg_beta = p->cg_beta;
     d.ls_g0 = p->ls_par_g0;
@@ -439,7 +543,10 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     d.k_minus = p->k_minus;
     d.eps_h = p->eps_h;
     double* x0 = at<double>(c->ws, L.off_vec) + (size_t)V_X0 * L.vstride;
-    if (!resume) HIP_TRY(hipMemcpyAsync(x0, xyz, 3 * (size_t)L.n * 8, hipMemcpyDeviceToDevice, st));
+    if (!resume)
+        for (int k = 0; k < L.n_sys; ++k)
+            HIP_TRY(hipMemcpyAsync(x0 + 3 * (size_t)c->sys[k].aoff, xyz + 3 * (size_t)c->sys[k].uoff,
+                                   3 * (size_t)c->sys[k].n * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(launch_kick(a, d, resume ? 1 : 0, trace_buffer(c), kTraceCap, st));
     if (!c->graph) {
         ff_status gs = build_graph(c);
@@ -448,41 +555,46 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     c->last_method = p->method;
     c->last_m = p->m;
     c->last_prec = p->precision;
-    // poll (phase, done, term, iters, evals): contiguous in the control block
-    const char* dev_state = c->ws + L.off_ctl + offsetof(Ctl, phase);
-    int32_t* hs = c->host_flag;
+    // poll (n_done, evals) of the batch
+    const char* dev_state = c->ws + L.off_batch;
+    uint32_t* hs = (uint32_t*)c->host_flag;
     int batch = 4;
-    int last_evals = -1;
+    uint32_t last_evals = 0xffffffffu;
     for (;;) {
         for (int k = 0; k < batch; ++k) HIP_TRY(hipGraphLaunch(c->graph, st));
-        HIP_TRY(hipMemcpyAsync(hs, dev_state, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hs, dev_state, sizeof(BatchState), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (hs[1]) break;
-        // every cycle that is not an accept pass evaluates; a batch without a
-        // new evaluation means the decision logic has stopped requesting work
-        if (hs[4] == last_evals) return fail(FF_ERR_HIP, "minimizer stalled in phase %d", hs[0]);
-        last_evals = hs[4];
+        if ((int)hs[0] >= L.n_sys) break;
+        // every cycle that is not only an accept pass evaluates; a batch of
+        // cycles without a new evaluation means the decision logic stopped
+        if (hs[1] == last_evals) return fail(FF_ERR_HIP, "minimizer stalled (%u of %d systems done)", hs[0], L.n_sys);
+        last_evals = hs[1];
         batch = std::min(batch * 2, 64);
     }
-    HIP_TRY(hipMemcpyAsync(c->host_ctl, c->ws + L.off_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    for (int k = 0; k < L.n_sys; ++k) {
+        const SysInfo& si = c->sys[k];
+        HIP_TRY(hipMemcpyAsync(c->host_ctl, c->ws + L.off_ctl + (size_t)k * L.ctl_stride, sizeof(Ctl),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const Ctl& h = *c->host_ctl;
+        const int slot = h.result_slot;
+        double* xr = at<double>(c->ws, L.off_vec) + (size_t)(V_X0 + slot) * L.vstride + 3 * (size_t)si.aoff;
+        HIP_TRY(hipMemcpyAsync(xyz + 3 * (size_t)si.uoff, xr, 3 * (size_t)si.n * 8, hipMemcpyDeviceToDevice, st));
+        ff_min_result& r = res[k];
+        r.term = h.term;
+        r.iters = h.iters - h.iters_base;
+        r.evals = h.evals;
+        r.evals_fp64 = h.evals64;
+        r.energy = h.e[slot];
+        r.grad_inf = h.ginf[slot];
+        r.grad_2 = std::sqrt(h.g2[slot]);
+    }
     HIP_TRY(hipStreamSynchronize(st));
-    const Ctl& h = *c->host_ctl;
-    const int slot = h.result_slot;
-    double* xr = at<double>(c->ws, L.off_vec) + (size_t)(V_X0 + slot) * L.vstride;
-    HIP_TRY(hipMemcpyAsync(xyz, xr, 3 * (size_t)L.n * 8, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    res->term = h.term;
-    res->iters = h.iters - h.iters_base;
-    res->evals = h.evals;
-    res->evals_fp64 = h.evals64;
-    res->energy = h.e[slot];
-    res->grad_inf = h.ginf[slot];
-    res->grad_2 = std::sqrt(h.g2[slot]);
     return FF_OK;
 }
 
 // Average duration (ms) of `reps` back-to-back launches of the pair kernel
-// alone at xyz, timed with HIP events recorded on the launch stream.
+// alone at xyz (all systems), timed with HIP events recorded on the launch stream.
 ff_status ff_time_pair(ff_ctx* c, const double* xyz, int32_t precision, int32_t reps, void* stream,
                        double* avg_ms) {
     g_err.clear();
@@ -512,9 +624,9 @@ ff_status ff_time_pair(ff_ctx* c, const double* xyz, int32_t precision, int32_t 
     return FF_OK;
 }
 
-// Per-iteration trace of the last ff_minimize call: out[3k..3k+2] = (E after
-// iteration k, accepted step h, evaluations so far).  Returns the number of
-// entries written (at most max_entries), or a negative ff_status.
+// Per-iteration trace of the last ff_minimize call (system 0): out[3k..3k+2]
+// = (E after iteration k, accepted step h, evaluations so far).  Returns the
+// number of entries written (at most max_entries), or a negative ff_status.
 int32_t ff_get_trace(ff_ctx* c, double* host_out, int32_t max_entries, void* stream) {
     if (!c || !host_out || max_entries < 0) return fail(FF_ERR_ARG, "bad arguments");
     stream = stream ? stream : (void*)c->own;

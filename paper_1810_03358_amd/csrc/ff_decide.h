@@ -82,6 +82,7 @@ __device__ inline void finish_done(Ctl* c, int slot) {
     c->done = 1;
     c->action = ACT_NONE;
     c->accept = 0;
+    if (c->batch) atomicAdd(&c->batch->n_done, 1u);
 }
 
 __device__ inline void finish(Ctl* c, int term) {
@@ -458,7 +459,7 @@ __device__ inline void after_accept(Ctl* c, const double* dots) {
     case M_CG: {
         // dots: [0] <g_new, g_old>, [1] <g_new, r_old>, [2] <r_old, g_old>
         const double beta = cg_beta(p.cg_beta, c->g2[old], c->g2[nw], dots[0], dots[1], dots[2]);
-        const int restart_every = p.cg_restart;
+        const int restart_every = p.cg_restart > 0 ? p.cg_restart : 3 * c->n_atoms;
         if ((c->iters + 1) % restart_every == 0) {
             c->steepest = 1;
         } else {
@@ -559,6 +560,7 @@ __device__ inline void after_accept(Ctl* c, const double* dots) {
 // After an evaluation (finalize's last workgroup).
 __device__ inline void after_eval(Ctl* c) {
     c->evals += 1;
+    if (c->batch) atomicAdd(&c->batch->evals, 1u);
     if (c->prec == P_FP64) c->evals64 += 1;
     const int t = c->target;
     c->slot_prec[t] = c->prec;

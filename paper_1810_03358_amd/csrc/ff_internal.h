@@ -1,9 +1,13 @@
 // Internal layout shared by the kernels and the host side of libff_mi355x.
 //
-// Workspace (caller-allocated device memory) =
-//   [control block | packed parameters | topology | tile tables |
-//    pair partials | bonded partials | reduction partials | FP64 vectors]
-// Every region starts on a 256-byte boundary.
+// A context holds a batch of one or more independent systems.  Workspace
+// (caller-allocated device memory) =
+//   [batch counters | per-system info | per-system control blocks |
+//    packed parameters | topology | tile tables | pair partials |
+//    bonded partials | reduction partials | FP64 vectors]
+// Every region starts on a 256-byte boundary.  Systems are concatenated: each
+// is padded to a multiple of the I-block size and occupies a contiguous range
+// of padded atoms (and 3x that range in every FP64 vector).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,7 +16,7 @@
 
 namespace ff {
 
-constexpr int kAtomAlign = 512;      // padded atom count is a multiple of this
+constexpr int kAtomAlign = 512;      // single-system padding (largest I-block)
 constexpr int kTile = 64;            // j-tile: one atom per lane of a wavefront
 constexpr int kExclWindow = 64;      // exclusions reach at most 64 atoms ahead
 constexpr int kMaxM = 32;            // largest L-BFGS memory
@@ -57,6 +61,12 @@ enum Phase : int32_t {
 };
 enum LsKind : int32_t { LSK_PAR = 0, LSK_H = 1 };
 enum LsHStage : int32_t { LSH_F0 = 0, LSH_F1 = 1, LSH_SHRINK = 2 };
+
+// Batch-wide counters polled by the host.
+struct BatchState {
+    uint32_t n_done;      // systems finished in the current ff_minimize
+    uint32_t evals;       // evaluations of all systems (progress watchdog)
+};
 
 struct MinParamsDev {
     int32_t method, m, max_iter, precision, linesearch, ls_K, cg_restart, certify, cg_beta, ls_g0, fgm_restart;
@@ -115,9 +125,11 @@ struct Ctl {
     double rho[kMaxM];
     double gram[kGramDim * kGramDim];        // over positions [s_0..s_{n-1}, y_0..y_{n-1}, g]
     int32_t result_slot;
-    // per-iteration trace (E, accepted h, evaluations so far)
+    // per-iteration trace (E, accepted h, evaluations so far); system 0 only
     double* trace_ptr;
     int32_t trace_cap, n_trace;
+    BatchState* batch;       // batch-wide counters
+    int32_t n_atoms;         // atoms of this system
 
     // ---- reduction tickets (last-block-done pattern)
     uint32_t ticket_fin, ticket_acc, ticket_prep;
@@ -141,9 +153,11 @@ constexpr int kNumTileConfigs = sizeof(kTileConfigs) / sizeof(kTileConfigs[0]);
 
 // ------------------------------------------------------------- tile tables
 struct ChunkInfo {        // one workgroup of the pair kernel
-    int32_t row;          // I-block index
-    int32_t t_begin, t_end;   // j-tiles [t_begin, t_end)
+    int32_t row;          // I-block index (global)
+    int32_t t_begin, t_end;   // j-tiles [t_begin, t_end) (global)
     int32_t unit_base;    // index of unit (row, t_begin) in the Fj partial array
+    int32_t sys;          // system the chunk belongs to
+    int32_t pad_[3];
 };
 struct RowInfo {          // one I-block
     int32_t unit_start;   // unit index of (row, t0)
@@ -152,15 +166,35 @@ struct RowInfo {          // one I-block
     int32_t n_chunks;
 };
 
+// One system of a batch.  Atom indices in its topology are local (0..n-1);
+// "global" indices count padded atoms over the whole batch.
+struct SysInfo {
+    int32_t n;            // atoms
+    int32_t np;           // padded atoms (multiple of the I-block size)
+    int32_t aoff;         // first padded atom (global); vectors start at 3*aoff
+    int32_t uoff;         // first atom in the caller's concatenated [sum n][3] arrays
+    int32_t row0, nb;     // first I-block (global) and count
+    int32_t chunk0, n_chunks;
+    int32_t n_bonds, n_angles, n_dihedrals;
+    int32_t bond0, angle0, dih0;   // first bond / angle / torsion in the batch-wide arrays
+    int32_t bonded_blocks, eb0;
+    int32_t fin_blocks, vec_blocks;
+    int32_t red0;         // first double of this system's reduction partials
+};
+
 struct Layout {
-    int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;
+    int32_t n_sys;
+    int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;   // n, np: totals over the batch
     int32_t n_bonds, n_angles, n_dihedrals, n_terms_slots, n_bonded_blocks;
     int32_t n_fin_blocks;
+    int32_t max_fin_blocks, max_vec_blocks, max_bonded_blocks;   // per-system maxima (grid x-extents)
     int32_t accept_bx;        // x-extent of the accept pass grid
     int32_t m_max;
     int32_t cfg;              // tile configuration index
     size_t vstride;           // doubles between vectors
+    size_t ctl_stride;        // bytes between control blocks
     // byte offsets
+    size_t off_batch, off_sys;
     size_t off_ctl, off_c12, off_c6, off_q, off_c12d, off_c6d, off_qd, off_excl;
     size_t off_chunks, off_rows, off_pi, off_pj, off_ep;
     size_t off_bond, off_bondp, off_angle, off_anglep, off_dih, off_dihp;
@@ -174,9 +208,9 @@ struct Layout {
 struct Args {
     Layout L;
     char* ws;
-    const double* xyz_in;    // direct mode: coordinates
-    double* e_out;           // direct mode: energy
-    double* g_out;           // direct mode: gradient or null
+    const double* xyz_in;    // direct mode: coordinates, [sum n][3] over the batch
+    double* e_out;           // direct mode: energies [n_sys]
+    double* g_out;           // direct mode: gradient [sum n][3] or null
     int32_t direct;          // 1: ff_energy_grad, 0: optimizer cycle
     int32_t direct_prec;
 };
@@ -184,8 +218,15 @@ struct Args {
 template <typename T>
 __host__ __device__ inline T* at(char* ws, size_t off) { return reinterpret_cast<T*>(ws + off); }
 
-__host__ __device__ inline double* vec(const Args& a, int32_t id) {
-    return at<double>(a.ws, a.L.off_vec) + (size_t)id * a.L.vstride;
+// Vector `id`, at the start of system `si`.
+__host__ __device__ inline double* vec(const Args& a, int32_t id, const SysInfo& si) {
+    return at<double>(a.ws, a.L.off_vec) + (size_t)id * a.L.vstride + 3 * (size_t)si.aoff;
+}
+
+__host__ __device__ inline SysInfo* sys_info(const Args& a) { return at<SysInfo>(a.ws, a.L.off_sys); }
+
+__host__ __device__ inline Ctl* ctl_at(const Args& a, int sys) {
+    return reinterpret_cast<Ctl*>(a.ws + a.L.off_ctl + (size_t)sys * a.L.ctl_stride);
 }
 
 // Coordinates of padding atoms (index >= n): far away, mutually separated,

@@ -7,7 +7,6 @@
 
 namespace ff {
 
-__device__ __forceinline__ Ctl* ctl_rw(const Args& a) { return at<Ctl>(a.ws, a.L.off_ctl); }
 
 // Wavefront sum of a double (xor butterfly).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -44,15 +43,15 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], bool first_is_max,
     __syncthreads();
 }
 
-// Last-block-done: returns true in every thread of the workgroup that
-// finished last.  The ticket counter is reset by that workgroup.
-__device__ __forceinline__ bool last_block(uint32_t* ticket) {
+// Last-block-done over `count` workgroups: returns true in every thread of
+// the workgroup that finished last, which also resets the ticket counter.
+__device__ __forceinline__ bool last_block(uint32_t* ticket, uint32_t count) {
     __shared__ int is_last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
+        is_last = (t == count - 1);
     }
     __syncthreads();
     if (is_last) {
@@ -82,7 +81,7 @@ __device__ __forceinline__ double block_sum_array(const double* p, int n, bool i
 // its I-block, then the j-side partials of every unit that holds its j-tile,
 // in a fixed order.  T is the storage type of the partials (FP32 mode: float).
 template <typename T>
-__device__ __forceinline__ void gather_pair(const Args& a, int atom, double& gx, double& gy, double& gz) {
+__device__ __forceinline__ void gather_pair(const Args& a, int row0, int atom, double& gx, double& gy, double& gz) {
     const Layout& L = a.L;
     const int row = atom / L.block, il = atom - row * L.block;
     const int t = atom / kTile, jl = atom - t * kTile;
@@ -94,7 +93,7 @@ __device__ __forceinline__ void gather_pair(const Args& a, int atom, double& gx,
         const T* p = Pi + ((size_t)ch * L.block + il) * 3;
         gx += (double)p[0]; gy += (double)p[1]; gz += (double)p[2];
     }
-    for (int r = 0; r <= row; ++r) {
+    for (int r = row0; r <= row; ++r) {
         const RowInfo rr = R[r];
         const T* p = Pj + ((size_t)(rr.unit_start + t - rr.t0) * kTile + jl) * 3;
         gx += (double)p[0]; gy += (double)p[1]; gz += (double)p[2];
@@ -105,22 +104,28 @@ __device__ __forceinline__ void gather_pair(const Args& a, int atom, double& gx,
 // (all chunks of its row), of the j partials of every unit holding it, and
 // of its bonded-term slots.  Then |g|_inf, |g|^2, optionally <g_base, d>, and
 // E = sum of the pair-workgroup and bonded-block energies.
+// Grid: (largest per-system block count, 1, systems); atoms are local to the
+// system, reductions and the decision step are per system.
 __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     const Layout& L = a.L;
-    Ctl* c = ctl_rw(a);
+    const int sys = blockIdx.z;
+    const SysInfo si = sys_info(a)[sys];
+    if ((int)blockIdx.x >= si.fin_blocks) return;
+    Ctl* c = ctl_at(a, sys);
     if (!a.direct && (c->action != ACT_EVAL || c->target < 0 || c->target >= kNumSlots)) return;
-    double* G = a.direct ? a.g_out : vec(a, V_G0 + c->target);
+    double* G = a.direct ? (a.g_out ? a.g_out + 3 * (size_t)si.uoff : nullptr) : vec(a, V_G0 + c->target, si);
     const bool want_slope = !a.direct && c->want_slope;
     const int atom = blockIdx.x * kFinBlock + threadIdx.x;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    if (atom < L.n) {
+    if (atom < si.n) {
+        const int ga = si.aoff + atom;      // global padded atom
         const bool p32 = a.direct ? a.direct_prec == 1 : c->prec == 1;
-        if (p32) gather_pair<float>(a, atom, gx, gy, gz);
-        else gather_pair<double>(a, atom, gx, gy, gz);
+        if (p32) gather_pair<float>(a, si.row0, ga, gx, gy, gz);
+        else gather_pair<double>(a, si.row0, ga, gx, gy, gz);
         const int* inc0 = at<int>(a.ws, L.off_inc_start);
         const int* inc = at<int>(a.ws, L.off_inc);
         const double* FB = at<double>(a.ws, L.off_fb);
-        for (int k = inc0[atom]; k < inc0[atom + 1]; ++k) {
+        for (int k = inc0[ga]; k < inc0[ga + 1]; ++k) {
             const double* p = FB + 3 * (size_t)inc[k];
             gx += p[0]; gy += p[1]; gz += p[2];
         }
@@ -131,32 +136,32 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     if (isnan(gx) || isnan(gy) || isnan(gz)) v[0] = __builtin_inf();
     v[1] = gx * gx + gy * gy + gz * gz;
     v[2] = 0.0;
-    if (want_slope && atom < L.n) {
-        const double* gb = vec(a, V_G0 + c->base);
-        const double* d = vec(a, V_D);
+    if (want_slope && atom < si.n) {
+        const double* gb = vec(a, V_G0 + c->base, si);
+        const double* d = vec(a, V_D, si);
         const size_t o = 3 * (size_t)atom;
         v[2] = gb[o] * d[o] + gb[o + 1] * d[o + 1] + gb[o + 2] * d[o + 2];
     }
-    double* red = at<double>(a.ws, L.off_red);
+    double* red = at<double>(a.ws, L.off_red) + si.red0;
     double tot[3];
     block_reduce<3>(v, true, tot);
     if (threadIdx.x == 0) { red[3 * blockIdx.x] = tot[0]; red[3 * blockIdx.x + 1] = tot[1]; red[3 * blockIdx.x + 2] = tot[2]; }
-    if (!last_block(&c->ticket_fin)) return;
-    // ---- last workgroup: totals in a fixed order
+    if (!last_block(&c->ticket_fin, si.fin_blocks)) return;
+    // ---- last workgroup of this system: totals in a fixed order
     double w[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kFinBlock) {
+    for (int b = threadIdx.x; b < si.fin_blocks; b += kFinBlock) {
         w[0] = fmax(w[0], red[3 * b]);
         w[1] += red[3 * b + 1];
         w[2] += red[3 * b + 2];
     }
     double gt[3];
     block_reduce<3>(w, true, gt);
-    const double e_pair = block_sum_array(at<double>(a.ws, L.off_ep), L.n_chunks);
-    const double e_bond = block_sum_array(at<double>(a.ws, L.off_eb), L.n_bonded_blocks);
+    const double e_pair = block_sum_array(at<double>(a.ws, L.off_ep) + si.chunk0, si.n_chunks);
+    const double e_bond = block_sum_array(at<double>(a.ws, L.off_eb) + si.eb0, si.bonded_blocks);
     if (threadIdx.x != 0) return;
     const double E = e_pair + e_bond;
     if (a.direct) {
-        if (a.e_out) *a.e_out = E;
+        if (a.e_out) a.e_out[sys] = E;
         return;
     }
     const int t = c->target;
@@ -173,26 +178,28 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
 // trial, or the FGM momentum point.  Rounding is kept explicit (no
 // contraction) so that trial points are reproducible.
 __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
-    const Ctl* c = ctl_rw(a);
+    const int sys = blockIdx.z;
+    const SysInfo si = sys_info(a)[sys];
+    const Ctl* c = ctl_at(a, sys);
     if (c->action != ACT_EVAL || c->point_mode == PM_USE) return;
     if (c->target < 0 || c->target >= kNumSlots || c->base < 0 || c->base >= kNumSlots) return;
     if (c->point_mode == PM_MOMENTUM && (c->prev < 0 || c->prev >= kNumSlots)) return;
-    const int n3 = 3 * a.L.n;
+    const int n3 = 3 * si.n;
     const int i = blockIdx.x * kFinBlock + threadIdx.x;
     if (i >= n3) return;
-    double* xt = vec(a, V_X0 + c->target);
-    const double* xb = vec(a, V_X0 + c->base);
+    double* xt = vec(a, V_X0 + c->target, si);
+    const double* xb = vec(a, V_X0 + c->base, si);
     if (c->point_mode == PM_MOMENTUM) {
-        const double* xp = vec(a, V_X0 + c->prev);
+        const double* xp = vec(a, V_X0 + c->prev, si);
         xt[i] = __dadd_rn(xb[i], __dmul_rn(c->beta, __dsub_rn(xb[i], xp[i])));
         return;
     }
-    double* d = vec(a, V_D);
+    double* d = vec(a, V_D, si);
     double di;
     if (c->point_mode == PM_DIR_TRIAL) {
-        double r = __dmul_rn(c->term_coef[0], vec(a, c->term_vec[0])[i]);
-        for (int k = 1; k < c->n_terms; ++k) r = __dadd_rn(r, __dmul_rn(c->term_coef[k], vec(a, c->term_vec[k])[i]));
-        if (c->write_r) vec(a, V_R)[i] = r;
+        double r = __dmul_rn(c->term_coef[0], vec(a, c->term_vec[0], si)[i]);
+        for (int k = 1; k < c->n_terms; ++k) r = __dadd_rn(r, __dmul_rn(c->term_coef[k], vec(a, c->term_vec[k], si)[i]));
+        if (c->write_r) vec(a, V_R, si)[i] = r;
         di = __ddiv_rn(r, c->dir_scale);
         d[i] = di;
     } else {
@@ -213,32 +220,34 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
 // strides over its share of the 3N elements and reduces once.  The last
 // block sums the per-block partials of every dot in block order.
 __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
-    Ctl* c = ctl_rw(a);
+    const int sys = blockIdx.z;
+    const SysInfo si = sys_info(a)[sys];
+    Ctl* c = ctl_at(a, sys);
     if (!c->accept) return;
-    const int n3 = 3 * a.L.n;
+    const int n3 = 3 * si.n;
     const int method = c->p.method;
     const int row = blockIdx.y;
     const int nh = method == M_LBFGS ? c->hist_n : 0;
     const bool active = (method == M_LBFGS && row <= nh) || (method == M_CG && row == 0);
-    double* red = at<double>(a.ws, a.L.off_red);
+    double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     const int nbx = gridDim.x;
     if (active) {
         double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        const double* xn = vec(a, V_X0 + c->acc_new);
-        const double* xo = vec(a, V_X0 + c->acc_old);
-        const double* gn = vec(a, V_G0 + c->acc_new);
-        const double* go = vec(a, V_G0 + c->acc_old);
+        const double* xn = vec(a, V_X0 + c->acc_new, si);
+        const double* xo = vec(a, V_X0 + c->acc_old, si);
+        const double* gn = vec(a, V_G0 + c->acc_new, si);
+        const double* go = vec(a, V_G0 + c->acc_old, si);
         const int stride = nbx * kFinBlock;
         if (method == M_CG) {
-            const double* r = vec(a, V_R);
+            const double* r = vec(a, V_R, si);
             for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 v[0] += gn[i] * go[i];
                 v[1] += gn[i] * r[i];
                 v[2] += r[i] * go[i];
             }
         } else if (row == 0) {
-            double* ss = vec(a, c->spare_s);
-            double* yy = vec(a, c->spare_y);
+            double* ss = vec(a, c->spare_s, si);
+            double* yy = vec(a, c->spare_y, si);
             for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 const double s = __dsub_rn(xn[i], xo[i]);
                 const double g = gn[i];
@@ -249,8 +258,8 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
                 v[3] += g * s; v[4] += g * y; v[5] += g * g;
             }
         } else {
-            const double* S = vec(a, c->hist_s[row - 1]);
-            const double* Y = vec(a, c->hist_y[row - 1]);
+            const double* S = vec(a, c->hist_s[row - 1], si);
+            const double* Y = vec(a, c->hist_y[row - 1], si);
             for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 const double s = __dsub_rn(xn[i], xo[i]);
                 const double g = gn[i];
@@ -292,9 +301,14 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
 
 // ---------------------------------------------------------------------- kick
 // Starts (or resumes) a minimization: one thread sets up the control block.
+// One workgroup per system (system 0 keeps the per-iteration trace).
 __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int trace_cap) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    Ctl* c = ctl_rw(a);
+    if (threadIdx.x != 0) return;
+    const int sys = blockIdx.x;
+    Ctl* c = ctl_at(a, sys);
+    if (sys != 0) trace = nullptr;
+    c->batch = at<BatchState>(a.ws, a.L.off_batch);
+    c->n_atoms = sys_info(a)[sys].n;
     if (resume) {
         c->p = p;
         c->done = 0;
@@ -339,10 +353,19 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
     request_eval(c, PM_USE, 0, 0);
 }
 
-// Clears the tickets and marks the context idle (after ff_create).
-__global__ void k_reset_ctl(Args a) {
+// Zeroes the batch counters (before a minimization starts).
+__global__ void k_reset_batch(Args a) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    Ctl* c = ctl_rw(a);
+    BatchState* b = at<BatchState>(a.ws, a.L.off_batch);
+    b->n_done = 0u;
+    b->evals = 0u;
+}
+
+// Clears the tickets and marks every system idle (after ff_create).
+__global__ void k_reset_ctl(Args a) {
+    if (threadIdx.x != 0) return;
+    Ctl* c = ctl_at(a, blockIdx.x);
+    c->batch = nullptr;
     c->ticket_fin = c->ticket_acc = c->ticket_prep = 0u;
     c->action = ACT_NONE;
     c->accept = 0;
@@ -352,25 +375,28 @@ __global__ void k_reset_ctl(Args a) {
 }
 
 hipError_t launch_finalize(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(a.L.n_fin_blocks), dim3(kFinBlock), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(a.L.max_fin_blocks, 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s) {
-    const int blocks = (3 * a.L.n + kFinBlock - 1) / kFinBlock;
-    if (which == 0) hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(kFinBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_accept, dim3(a.L.accept_bx, kMaxM + 1), dim3(kFinBlock), 0, s, a);
+    if (which == 0)
+        hipLaunchKernelGGL(k_prepare, dim3(a.L.max_vec_blocks, 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_accept, dim3(a.L.accept_bx, kMaxM + 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_kick(const Args& a, const MinParamsDev& p, int resume, double* trace, int trace_cap,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_kick, dim3(1), dim3(64), 0, s, a, p, resume, trace, trace_cap);
+    hipLaunchKernelGGL(k_reset_batch, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_kick, dim3(a.L.n_sys), dim3(64), 0, s, a, p, resume, trace, trace_cap);
     return hipGetLastError();
 }
 
 hipError_t launch_reset(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_reset_ctl, dim3(a.L.n_sys), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_reset_batch, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

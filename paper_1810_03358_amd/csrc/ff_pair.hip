@@ -46,17 +46,17 @@ __device__ __forceinline__ double rotate_down(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ const Ctl* ctl_of(const Args& a) { return at<Ctl>(a.ws, a.L.off_ctl); }
-
-__device__ __forceinline__ bool eval_active(const Args& a, int prec) {
+// Does system `sys` evaluate in precision `prec` this cycle?
+__device__ __forceinline__ bool eval_active(const Args& a, int sys, int prec) {
     if (a.direct) return a.direct_prec == prec;
-    const Ctl* c = ctl_of(a);
+    const Ctl* c = ctl_at(a, sys);
     return c->action == ACT_EVAL && c->prec == prec && c->target >= 0 && c->target < kNumSlots;
 }
 
-__device__ __forceinline__ const double* eval_coords(const Args& a) {
-    if (a.direct) return a.xyz_in;
-    return vec(a, V_X0 + ctl_of(a)->target);
+// Coordinates of system `si` for this evaluation ([n][3], local atom index).
+__device__ __forceinline__ const double* eval_coords(const Args& a, int sys, const SysInfo& si) {
+    if (a.direct) return a.xyz_in + 3 * (size_t)si.uoff;
+    return vec(a, V_X0 + ctl_at(a, sys)->target, si);
 }
 
 __device__ __forceinline__ void load_pos(const double* X, int32_t atom, int32_t n, double* p) {
@@ -75,11 +75,12 @@ __device__ __forceinline__ void load_pos(const double* X, int32_t atom, int32_t 
 // per-block partial.
 // Energy of bonded term t (bonds, then angles, then dihedrals) and its
 // gradient on each of its atoms, written to the term's own slots.
-__device__ double bonded_term(const Args& a, const double* X, int t) {
+__device__ double bonded_term(const Args& a, const double* X, const SysInfo& si, int t) {
     const Layout& L = a.L;
     double e = 0.0;
     double* FB = at<double>(a.ws, L.off_fb);
-    if (t < L.n_bonds) {
+    if (t < si.n_bonds) {
+        t += si.bond0;
         const int2 b = at<int2>(a.ws, L.off_bond)[t];
         const double2 kp = at<double2>(a.ws, L.off_bondp)[t];   // (K, r0)
         double d[3], r2 = 0.0;
@@ -90,8 +91,8 @@ __device__ double bonded_term(const Args& a, const double* X, int t) {
         const double s = 2.0 * kp.x * dr / r;
         double* o = FB + 6 * (size_t)t;
         for (int c = 0; c < 3; ++c) { o[c] = s * d[c]; o[3 + c] = -s * d[c]; }
-    } else if (t < L.n_bonds + L.n_angles) {
-        const int k = t - L.n_bonds;
+    } else if (t < si.n_bonds + si.n_angles) {
+        const int k = t - si.n_bonds + si.angle0;
         const int* ia = at<int>(a.ws, L.off_angle) + 3 * k;
         const double2 kp = at<double2>(a.ws, L.off_anglep)[k];  // (K, theta0)
         double u[3], v[3];
@@ -120,8 +121,8 @@ __device__ double bonded_term(const Args& a, const double* X, int t) {
             o[3 + c] = -(gi + gk);
             o[6 + c] = gk;
         }
-    } else if (t < L.n_bonds + L.n_angles + L.n_dihedrals) {
-        const int k = t - L.n_bonds - L.n_angles;
+    } else if (t < si.n_bonds + si.n_angles + si.n_dihedrals) {
+        const int k = t - si.n_bonds - si.n_angles + si.dih0;
         const int* id = at<int>(a.ws, L.off_dih) + 4 * k;
         const double* V = at<double>(a.ws, L.off_dihp) + 4 * k;
         // F = x_a - x_b, G = x_b - x_c, H = x_d - x_c (Blondel and Karplus 1996)
@@ -165,12 +166,10 @@ __device__ double bonded_term(const Args& a, const double* X, int t) {
     return e;
 }
 
-__device__ double bonded_term(const Args& a, const double* X, int t);
-
-__device__ void bonded_block(const Args& a, const double* X, int blk, int nthreads) {
+__device__ void bonded_block(const Args& a, const double* X, const SysInfo& si, int blk, int nthreads) {
     double e = 0.0;
     const int first = blk * kBondedPerBlock;
-    for (int t = first + (int)threadIdx.x; t < first + kBondedPerBlock; t += nthreads) e += bonded_term(a, X, t);
+    for (int t = first + (int)threadIdx.x; t < first + kBondedPerBlock; t += nthreads) e += bonded_term(a, X, si, t);
     // deterministic block sum of the term energies
     __shared__ double red[kBondedPerBlock];
     red[threadIdx.x] = e;
@@ -179,13 +178,17 @@ __device__ void bonded_block(const Args& a, const double* X, int blk, int nthrea
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) at<double>(a.ws, a.L.off_eb)[blk] = red[0];
+    if (threadIdx.x == 0) at<double>(a.ws, a.L.off_eb)[si.eb0 + blk] = red[0];
 }
 
 // Bonded terms of one evaluation (any precision mode: always FP64).
+// Grid: (largest per-system block count, 1, systems).
 __global__ void __launch_bounds__(kBondedPerBlock) k_bonded(Args a) {
-    if (!(eval_active(a, 0) || eval_active(a, 1))) return;
-    bonded_block(a, eval_coords(a), blockIdx.x, kBondedPerBlock);
+    const int sys = blockIdx.z;
+    const SysInfo si = sys_info(a)[sys];
+    if ((int)blockIdx.x >= si.bonded_blocks) return;
+    if (!(eval_active(a, sys, 0) || eval_active(a, sys, 1))) return;
+    bonded_block(a, eval_coords(a, sys, si), si, blockIdx.x, kBondedPerBlock);
 }
 
 // ---------------------------------------------------------------- FP32 pairs
@@ -315,14 +318,15 @@ __device__ __forceinline__ void block_energy_store(double e, double* out) {
 
 template <int WAVES, int IPL>
 __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
-    if (!eval_active(a, 1)) return;
-    const double* X = eval_coords(a);
     const Layout& L = a.L;
     const int wg = blockIdx.x;
-    constexpr int B = 64 * WAVES * IPL;
     const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
+    if (!eval_active(a, ch.sys, 1)) return;
+    const SysInfo si = sys_info(a)[ch.sys];
+    const double* X = eval_coords(a, ch.sys, si);
+    constexpr int B = 64 * WAVES * IPL;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = L.n;
+    const int n = si.n, aoff = si.aoff;
     const float* C12 = at<float>(a.ws, L.off_c12);
     const float* C6 = at<float>(a.ws, L.off_c6);
     const float* Q = at<float>(a.ws, L.off_q);
@@ -338,7 +342,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
     for (int k = 0; k < IPL; ++k) {
         const int i = i0 + k * 64;
         double p[3];
-        load_pos(X, i, n, p);
+        load_pos(X, i - aoff, n, p);
         float4 lo;
         split(p[0], I.xh[k], lo.x);
         split(p[1], I.yh[k], lo.y);
@@ -375,7 +379,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
         if (threadIdx.x < kTile) {
             const int j = J0 + threadIdx.x;
             double p[3];
-            load_pos(X, j, n, p);
+            load_pos(X, j - aoff, n, p);
             float4 h, l;
             split(p[0], h.x, l.x);
             split(p[1], h.y, l.y);
@@ -486,14 +490,15 @@ __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const d
 
 template <int WAVES, int IPL>
 __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
-    if (!eval_active(a, 0)) return;
-    const double* X = eval_coords(a);
     const Layout& L = a.L;
     const int wg = blockIdx.x;
-    constexpr int B = 64 * WAVES * IPL;
     const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
+    if (!eval_active(a, ch.sys, 0)) return;
+    const SysInfo si = sys_info(a)[ch.sys];
+    const double* X = eval_coords(a, ch.sys, si);
+    constexpr int B = 64 * WAVES * IPL;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = L.n;
+    const int n = si.n, aoff = si.aoff;
     const double* C12 = at<double>(a.ws, L.off_c12d);
     const double* C6 = at<double>(a.ws, L.off_c6d);
     const double* Q = at<double>(a.ws, L.off_qd);
@@ -507,7 +512,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
     for (int k = 0; k < IPL; ++k) {
         const int i = I0 + wave * 64 * IPL + k * 64 + lane;
         double p[3];
-        load_pos(X, i, n, p);
+        load_pos(X, i - aoff, n, p);
         xi[k] = p[0]; yi[k] = p[1]; zi[k] = p[2];
         c12i[k] = C12[i]; c6i[k] = C6[i]; qi[k] = Q[i];
         excl[k] = EX[i];
@@ -525,7 +530,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
         if (threadIdx.x < kTile) {
             const int j = J0 + threadIdx.x;
             double p[3];
-            load_pos(X, j, n, p);
+            load_pos(X, j - aoff, n, p);
             const double4 h = make_double4(p[0], p[1], p[2], Q[j]);
             const double2 c = make_double2(C12[j], C6[j]);
             s_xq[threadIdx.x] = h; s_xq[threadIdx.x + kTile] = h;
@@ -586,7 +591,7 @@ hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
 }
 
 hipError_t launch_bonded(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bonded, dim3(a.L.n_bonded_blocks), dim3(kBondedPerBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bonded, dim3(a.L.max_bonded_blocks, 1, a.L.n_sys), dim3(kBondedPerBlock), 0, s, a);
     return hipGetLastError();
 }
 

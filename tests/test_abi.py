@@ -97,3 +97,21 @@ def test_product_package_does_not_import_the_oracle():
                     if isinstance(node, (ast.Import, ast.ImportFrom)):
                         names = [a.name for a in node.names] + [getattr(node, "module", "") or ""]
                         assert not any(n.split(".")[0] == "oracle" for n in names), f
+
+
+def test_batch_workspace_and_validation():
+    import numpy as np
+    a, b = chain_system(50, 1), chain_system(300, 2)
+    hs = [ff.HostSystem(a), ff.HostSystem(b)]
+    arr = (N.FFSystem * 2)(*[h.c for h in hs])
+    lib = N.load()
+    nb = lib.ff_workspace_bytes_batch(arr, 2, 10)
+    assert nb > 0 and nb % 256 == 0
+    assert lib.ff_workspace_bytes_batch(arr, 0, 10) == 0
+    bad = dict(b, bonds=b["bonds"].copy())
+    bad["bonds"][7, 0] = 300
+    hs2 = [ff.HostSystem(a), ff.HostSystem(bad)]
+    arr2 = (N.FFSystem * 2)(*[h.c for h in hs2])
+    ctx = C.c_void_p()
+    st = lib.ff_create_batch(arr2, 2, C.c_void_p(256), 1 << 40, 10, None, C.byref(ctx))
+    assert st == ff.FF_ERR_ARG and "system 1" in N.last_error()
