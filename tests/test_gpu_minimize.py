@@ -6,9 +6,10 @@ decisions (equal evaluation counts after every iteration), energies within
 out the trajectories separate at the rate the problem itself amplifies
 rounding: perturbing the oracle's E and grad E by one ulp (relative 2^-52)
 moves its own energies by 1e-11 (GD), 1e-9 (CG), 4e-12 (L-BFGS) and 2e-3
-(FGM, whose momentum is unstable on this workload) by iteration 50, with
-identical decisions.  So iterations 20..50 are gated at 1e-6 relative for
-GD, CG and L-BFGS, and FGM's energies are compared up to iteration 30.
+(FGM, whose momentum is unstable on this workload) by iteration 50, and by
+5e-6 at iteration 40 for FGM with restarts, with identical decisions.  So
+iterations 20..50 are gated at 1e-6 relative for GD, CG and L-BFGS, and the
+FGM variants' energies are compared up to iteration 30.
 FP32 mode is checked on its final state: the certified energy and gradient
 norm reported for the returned point must be what the oracle computes there.
 """
@@ -112,7 +113,7 @@ def test_fp64_fgm_with_restart():
     ref = oracle_run(s, "fgm", max_iter=40, fgm_restart=True)
     r, x, tr, _ = gpu_run(s, "fgm", max_iter=40, fgm_restart=True)
     assert r["term"] == ref.term and r["evals"] == ref.evals
-    compare_traces(tr, ref, 40)
+    compare_traces(tr, ref, 40, loose_until=30)
 
 
 @pytest.mark.parametrize("K", [2, 3])
