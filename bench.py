@@ -30,6 +30,33 @@ PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_FP32_PACKED_TFLOPS = 157.3
 
 
+PAIR_SOURCES = ["paper_1810_03358_amd/csrc/ff_pair.hip", "paper_1810_03358_amd/csrc/ff_internal.h"]
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary (copy-kernel calibrated), or None when there is no
+    summary for this workload or the kernel sources changed since it was
+    taken."""
+    import hashlib
+    if precision != "fp32":
+        return None
+    path = os.path.join(ROOT, "profiles", f"k_pair32_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("source_sha256 (ff_pair.hip + ff_internal.h at measurement)") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def non_excluded_pairs(n: int) -> int:
     # chain topology: 1-2 and 1-3 pairs excluded
     return n * (n - 1) // 2 - max(0, n - 1) - max(0, n - 2)
@@ -153,7 +180,8 @@ def main():
             "peak": PEAK_FP32_TFLOPS if args.precision == "fp32" else 78.6,
             "unit": "TFLOP/s",
             "frac": achieved / (PEAK_FP32_TFLOPS if args.precision == "fp32" else 78.6),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, args.precision),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel_ms": ms_pair,
             "flops_per_pair": FLOPS_PER_PAIR,
             "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,

@@ -86,7 +86,7 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     if (n_sys > 1) { L.cfg = 0; L.chunk = 4; }
     else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
     else if (n_max <= 16384) { L.cfg = 1; L.chunk = 4; }
-    else { L.cfg = 2; L.chunk = 8; }
+    else { L.cfg = 3; L.chunk = 8; }
     if (const char* env = std::getenv("FF_PAIR_CONFIG")) {
         int cfg = -1, chunk = 0;
         const int got = std::sscanf(env, "%d,%d", &cfg, &chunk);
