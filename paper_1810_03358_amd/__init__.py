@@ -71,13 +71,50 @@ def _stream_ptr(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def tile_configs() -> list:
+    """Shapes of the pair-kernel tile configurations:
+    (block, waves32, ipl32, waves64, ipl64) per index."""
+    lib = N.load()
+    out = []
+    for k in range(int(lib.ff_num_tile_configs())):
+        v = [C.c_int32() for _ in range(5)]
+        _check(lib.ff_tile_config_info(k, *[C.byref(x) for x in v]), "ff_tile_config_info")
+        out.append(tuple(x.value for x in v))
+    return out
+
+
+def autotune(system, x: torch.Tensor, precision: str | int = "fp32", reps: int = 5, device="cuda", stream=None):
+    """Time every tile configuration and chunk length on E+grad evaluations of
+    ``system`` (one dict or a list) at ``x`` and return
+    ((tile_config, chunk), ms_per_eval) of the fastest."""
+    lib = N.load()
+    systems = list(system) if isinstance(system, (list, tuple)) else [system]
+    hosts = [HostSystem(d) for d in systems]
+    arr = (N.FFSystem * len(hosts))(*[h.c for h in hosts])
+    nbytes = int(lib.ff_autotune_workspace_bytes(arr, len(hosts)))
+    if nbytes == 0:
+        raise FFError(FF_ERR_ARG, "ff_autotune_workspace_bytes")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+    ptr = (ws.data_ptr() + 255) // 256 * 256
+    if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()):
+        raise ValueError("coordinates must be a contiguous float64 CUDA tensor")
+    cfg, ch, ms = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib.ff_autotune(arr, len(hosts), C.c_void_p(x.data_ptr()), C.c_void_p(ptr), nbytes,
+                           int(PRECISIONS.get(precision, precision)), int(reps), _stream_ptr(stream), C.byref(cfg), C.byref(ch),
+                           C.byref(ms)), "ff_autotune")
+    del ws
+    return (cfg.value, ch.value), ms.value
+
+
 class Context:
     """Prepared system(s) on one GPU: workspace (torch uint8 tensor) + ff_ctx.
 
     ``system`` is one system dict or a list of them (a batch, minimized
     together; coordinates are then concatenated in list order)."""
 
-    def __init__(self, system, m_max: int = 10, device="cuda", stream=None):
+    def __init__(self, system, m_max: int = 10, device="cuda", stream=None, tiling=None):
+        """``tiling`` = (tile_config, chunk) names the pair-kernel tiling
+        (e.g. from :func:`autotune`); None lets the library choose."""
         lib = N.load()
         self.is_batch = isinstance(system, (list, tuple))
         systems = list(system) if self.is_batch else [system]
@@ -88,17 +125,29 @@ class Context:
         self.n = sum(self.sizes)
         self.device = torch.device(device)
         self._sys_array = (N.FFSystem * self.n_sys)(*[h.c for h in self.hosts])
-        nbytes = int(lib.ff_workspace_bytes_batch(self._sys_array, self.n_sys, m_max))
+        if tiling is None:
+            nbytes = int(lib.ff_workspace_bytes_batch(self._sys_array, self.n_sys, m_max))
+        else:
+            nbytes = int(lib.ff_workspace_bytes_tiled(self._sys_array, self.n_sys, m_max, int(tiling[0]),
+                                                      int(tiling[1])))
         if nbytes == 0:
-            raise FFError(FF_ERR_ARG, "ff_workspace_bytes_batch")
+            raise FFError(FF_ERR_ARG, "ff_workspace_bytes")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         ctx = C.c_void_p()
-        _check(lib.ff_create_batch(self._sys_array, self.n_sys, C.c_void_p(self._ws_ptr), nbytes, m_max,
-                                   _stream_ptr(stream), C.byref(ctx)), "ff_create_batch")
+        if tiling is None:
+            _check(lib.ff_create_batch(self._sys_array, self.n_sys, C.c_void_p(self._ws_ptr), nbytes, m_max,
+                                       _stream_ptr(stream), C.byref(ctx)), "ff_create_batch")
+        else:
+            _check(lib.ff_create_tiled(self._sys_array, self.n_sys, C.c_void_p(self._ws_ptr), nbytes, m_max,
+                                       int(tiling[0]), int(tiling[1]), _stream_ptr(stream), C.byref(ctx)),
+                   "ff_create_tiled")
         self._ctx = ctx
         self.m_max = m_max
+        cfg, ch = C.c_int32(), C.c_int32()
+        _check(lib.ff_get_tiling(self._ctx, C.byref(cfg), C.byref(ch)), "ff_get_tiling")
+        self.tiling = (cfg.value, ch.value)
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -48,7 +48,8 @@ class FFMinResult(C.Structure):
 
 EXPORTS = ("ff_workspace_bytes", "ff_workspace_bytes_batch", "ff_create", "ff_create_batch", "ff_batch_size",
            "ff_destroy", "ff_energy_grad", "ff_minimize", "ff_get_trace", "ff_time_pair", "ff_default_params",
-           "ff_last_error")
+           "ff_last_error", "ff_num_tile_configs", "ff_tile_config_info", "ff_workspace_bytes_tiled",
+           "ff_create_tiled", "ff_get_tiling", "ff_autotune_workspace_bytes", "ff_autotune")
 
 _lib = None
 
@@ -86,6 +87,23 @@ def load():
     lib.ff_time_pair.restype = C.c_int
     lib.ff_default_params.argtypes = [C.POINTER(FFMinParams)]
     lib.ff_default_params.restype = None
+    _ip = C.POINTER(C.c_int32)
+    lib.ff_num_tile_configs.argtypes = []
+    lib.ff_num_tile_configs.restype = C.c_int32
+    lib.ff_tile_config_info.argtypes = [C.c_int32, _ip, _ip, _ip, _ip, _ip]
+    lib.ff_tile_config_info.restype = C.c_int
+    lib.ff_workspace_bytes_tiled.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    lib.ff_workspace_bytes_tiled.restype = C.c_size_t
+    lib.ff_create_tiled.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_void_p, C.c_size_t, C.c_int32,
+                                    C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.ff_create_tiled.restype = C.c_int
+    lib.ff_get_tiling.argtypes = [C.c_void_p, _ip, _ip]
+    lib.ff_get_tiling.restype = C.c_int
+    lib.ff_autotune_workspace_bytes.argtypes = [C.POINTER(FFSystem), C.c_int32]
+    lib.ff_autotune_workspace_bytes.restype = C.c_size_t
+    lib.ff_autotune.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
+                                C.c_int32, C.c_void_p, _ip, _ip, _dp]
+    lib.ff_autotune.restype = C.c_int
     lib.ff_last_error.argtypes = []
     lib.ff_last_error.restype = C.c_char_p
     _lib = lib

@@ -67,10 +67,12 @@ static ff_status fail(ff_status st, const char* fmt, ...) {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ layout
-// Tile configuration: a single system picks its I-block by size; a batch of
-// several systems uses 64-atom I-blocks so that small systems are padded to a
-// multiple of 64 only.  "FF_PAIR_CONFIG=cfg[,chunk]" overrides (tuning).
-static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, std::vector<SysInfo>* out) {
+// Tile configuration: explicit (cfg >= 0, chunk >= 1), or by default a single
+// system picks its I-block by size and a batch of several systems uses 64-atom
+// I-blocks so that small systems are padded to a multiple of 64 only
+// ("FF_PAIR_CONFIG=cfg[,chunk]" overrides the default).
+static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, std::vector<SysInfo>* out,
+                        int32_t cfg_req = -1, int32_t chunk_req = 0) {
     std::memset(&L, 0, sizeof L);
     if (!s || n_sys < 1) return false;
     if (m_max < 0 || m_max > kMaxM) return false;
@@ -87,11 +89,15 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
     else if (n_max <= 16384) { L.cfg = 1; L.chunk = 4; }
     else { L.cfg = 3; L.chunk = 8; }
-    if (const char* env = std::getenv("FF_PAIR_CONFIG")) {
+    if (cfg_req >= 0) {
+        if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk) return false;
+        L.cfg = cfg_req;
+        L.chunk = chunk_req;
+    } else if (const char* env = std::getenv("FF_PAIR_CONFIG")) {
         int cfg = -1, chunk = 0;
         const int got = std::sscanf(env, "%d,%d", &cfg, &chunk);
         if (got >= 1 && cfg >= 0 && cfg < kNumTileConfigs) L.cfg = cfg;
-        if (got == 2 && chunk >= 1 && chunk <= 4096) L.chunk = chunk;
+        if (got == 2 && chunk >= 1 && chunk <= kMaxChunk) L.chunk = chunk;
     }
     L.block = kTileConfigs[L.cfg].block;
     std::vector<SysInfo> sys(n_sys);
@@ -128,10 +134,10 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
         si.bonded_blocks = std::max(1, (terms + kBondedPerBlock - 1) / kBondedPerBlock);
         si.eb0 = ebo;
         ebo += si.bonded_blocks;
-        si.fin_blocks = (si.n + kFinBlock - 1) / kFinBlock;
+        si.fin_blocks = (si.n + kTile - 1) / kTile;      // one finalize workgroup per tile
         si.vec_blocks = (3 * si.n + kFinBlock - 1) / kFinBlock;
         si.red0 = (int32_t)red;
-        red += std::max((size_t)si.fin_blocks * 3, (size_t)L.accept_bx * (kMaxM + 1) * 6);
+        red += std::max((size_t)si.fin_blocks * 4, (size_t)L.accept_bx * (kMaxM + 1) * 6);
         L.max_fin_blocks = std::max(L.max_fin_blocks, si.fin_blocks);
         L.max_vec_blocks = std::max(L.max_vec_blocks, si.vec_blocks);
         L.max_bonded_blocks = std::max(L.max_bonded_blocks, si.bonded_blocks);
@@ -247,6 +253,29 @@ size_t ff_workspace_bytes_batch(const ff_system* sys, int32_t n_sys, int32_t m_m
     return L.total;
 }
 
+size_t ff_workspace_bytes_tiled(const ff_system* sys, int32_t n_sys, int32_t m_max, int32_t tile_config,
+                                int32_t chunk) {
+    Layout L;
+    if (tile_config < 0 || !make_layout(sys, n_sys, m_max, L, nullptr, tile_config, chunk)) return 0;
+    return L.total;
+}
+
+int32_t ff_num_tile_configs(void) { return kNumTileConfigs; }
+
+ff_status ff_tile_config_info(int32_t cfg, int32_t* block, int32_t* waves32, int32_t* ipl32, int32_t* waves64,
+                              int32_t* ipl64) {
+    g_err.clear();
+    if (cfg < 0 || cfg >= kNumTileConfigs) return fail(FF_ERR_ARG, "tile configuration %d outside [0, %d)", cfg,
+                                                       kNumTileConfigs);
+    const TileConfig& t = kTileConfigs[cfg];
+    if (block) *block = t.block;
+    if (waves32) *waves32 = t.waves32;
+    if (ipl32) *ipl32 = t.ipl32;
+    if (waves64) *waves64 = t.waves64;
+    if (ipl64) *ipl64 = t.ipl64;
+    return FF_OK;
+}
+
 size_t ff_workspace_bytes(const ff_system* sys, int32_t m_max) { return ff_workspace_bytes_batch(sys, 1, m_max); }
 
 void ff_default_params(ff_min_params* p) {
@@ -273,8 +302,8 @@ const char* ff_last_error(void) { return g_err.c_str(); }
 
 int32_t ff_batch_size(const ff_ctx* c) { return c ? c->L.n_sys : 0; }
 
-ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes, int32_t m_max,
-                          void* stream, ff_ctx** out) {
+static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes,
+                             int32_t m_max, int32_t cfg_req, int32_t chunk_req, void* stream, ff_ctx** out) {
     g_err.clear();
     if (!out) return fail(FF_ERR_ARG, "out is null");
     *out = nullptr;
@@ -284,7 +313,10 @@ ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspa
     if (m_max < 0 || m_max > kMaxM) return fail(FF_ERR_ARG, "m_max must be in [0, %d]", kMaxM);
     Layout L;
     std::vector<SysInfo> sys;
-    if (!make_layout(systems, n_sys, m_max, L, &sys)) return fail(FF_ERR_ARG, "invalid sizes");
+    if (cfg_req >= 0 && (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk))
+        return fail(FF_ERR_ARG, "tile configuration %d / chunk %d outside [0, %d) / [1, %d]", cfg_req, chunk_req,
+                    kNumTileConfigs, kMaxChunk);
+    if (!make_layout(systems, n_sys, m_max, L, &sys, cfg_req, chunk_req)) return fail(FF_ERR_ARG, "invalid sizes");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(FF_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
     if (ws_bytes < L.total) return fail(FF_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
     std::vector<uint64_t> excl(L.np, 0ull);
@@ -432,6 +464,98 @@ ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspa
         return fail(FF_ERR_HIP, "stream creation failed");
     }
     *out = c;
+    return FF_OK;
+}
+
+ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes, int32_t m_max,
+                          void* stream, ff_ctx** out) {
+    return create_impl(systems, n_sys, workspace, ws_bytes, m_max, -1, 0, stream, out);
+}
+
+ff_status ff_create_tiled(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes,
+                          int32_t m_max, int32_t tile_config, int32_t chunk, void* stream, ff_ctx** out) {
+    if (tile_config < 0) {
+        g_err = "tile_config must be >= 0 (ff_create_batch picks one itself)";
+        if (out) *out = nullptr;
+        return FF_ERR_ARG;
+    }
+    return create_impl(systems, n_sys, workspace, ws_bytes, m_max, tile_config, chunk, stream, out);
+}
+
+ff_status ff_get_tiling(const ff_ctx* c, int32_t* tile_config, int32_t* chunk) {
+    if (!c) {
+        g_err = "context is null";
+        return FF_ERR_ARG;
+    }
+    if (tile_config) *tile_config = c->L.cfg;
+    if (chunk) *chunk = c->L.chunk;
+    return FF_OK;
+}
+
+// Candidate chunk lengths of the autotuner (j-tiles per pair workgroup).
+static const int32_t kTuneChunks[] = {1, 2, 4, 8, 16};
+
+size_t ff_autotune_workspace_bytes(const ff_system* systems, int32_t n_sys) {
+    size_t best = 0;
+    for (int cfg = 0; cfg < kNumTileConfigs; ++cfg)
+        for (int32_t ch : kTuneChunks) {
+            Layout L;
+            if (!make_layout(systems, n_sys, 0, L, nullptr, cfg, ch)) return 0;
+            best = std::max(best, L.total);
+        }
+    return best ? best + align256(8 * (size_t)n_sys) : 0;
+}
+
+ff_status ff_autotune(const ff_system* systems, int32_t n_sys, const double* xyz, void* workspace,
+                      size_t ws_bytes, int32_t precision, int32_t reps, void* stream, int32_t* tile_config,
+                      int32_t* chunk, double* ms_per_eval) {
+    g_err.clear();
+    if (!systems || n_sys < 1 || !xyz || !workspace || reps < 1 || !tile_config || !chunk)
+        return fail(FF_ERR_ARG, "bad arguments");
+    if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
+    if ((uintptr_t)workspace & 255) return fail(FF_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    const size_t tail = align256(8 * (size_t)n_sys);
+    if (ws_bytes < tail + 256) return fail(FF_ERR_WORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    // the energies of the timed evaluations go to the tail of the workspace
+    const size_t usable = (ws_bytes - tail) & ~(size_t)255;
+    double* e_out = (double*)((char*)workspace + usable);
+    double best_ms = 0.0;
+    int32_t best_cfg = -1, best_chunk = 0;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(FF_ERR_HIP, "event"); }
+    ff_status result = FF_OK;
+    std::vector<double> e_tmp;
+    for (int cfg = 0; cfg < kNumTileConfigs && result == FF_OK; ++cfg) {
+        for (int32_t ch : kTuneChunks) {
+            Layout L;
+            if (!make_layout(systems, n_sys, 0, L, nullptr, cfg, ch) || L.total > usable) continue;
+            ff_ctx* c = nullptr;
+            ff_status s = create_impl(systems, n_sys, workspace, usable, 0, cfg, ch, stream, &c);
+            if (s) { result = s; break; }
+            double* eo = e_out;
+            hipError_t e = ff_energy_grad(c, xyz, eo, nullptr, precision, st) == FF_OK ? hipSuccess : hipErrorUnknown;
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = ff_energy_grad(c, xyz, eo, nullptr, precision, st) == FF_OK ? hipSuccess : hipErrorUnknown;
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            ff_destroy(c);
+            if (e != hipSuccess) { result = fail(FF_ERR_HIP, "autotune timing failed"); break; }
+            const double per = (double)ms / reps;
+            if (best_cfg < 0 || per < best_ms) { best_ms = per; best_cfg = cfg; best_chunk = ch; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != FF_OK) return result;
+    if (best_cfg < 0) return fail(FF_ERR_WORKSPACE, "no tile configuration fits in %zu bytes", ws_bytes);
+    *tile_config = best_cfg;
+    *chunk = best_chunk;
+    if (ms_per_eval) *ms_per_eval = best_ms;
     return FF_OK;
 }
 

@@ -2,10 +2,10 @@
 // (section 5.2, Algorithms 6 and 5) and the methods GD (section 4, eq. 4),
 // FGM (Algorithm 1), CG with the Polak-Ribiere-Polyak beta (Algorithm 2) and
 // L-BFGS (Algorithms 3 and 4), written as a state machine that advances once
-// per energy+gradient evaluation and once per accepted step.  It runs in a
-// single thread (the last workgroup of the finalize or accept kernel); all
-// its state lives in the control block, so iterates never go back to the
-// host.
+// per energy+gradient evaluation and once per accepted step.  It runs in one
+// thread of the last workgroup of the finalize or accept kernel (the L-BFGS
+// coefficient algebra runs on that whole workgroup just before it); all its
+// state lives in the control block, so iterates never go back to the host.
 //
 // Readings where the paper is silent (identical to the rules of the CPU
 // reference implementation used to check this library):
@@ -98,11 +98,18 @@ __device__ inline void finish(Ctl* c, int term) {
     finish_done(c, slot);
 }
 
-// Re-evaluate `slot` in FP64 (precision escalation of the mixed mode).
+__device__ inline void lbfgs_clear(Ctl* c);
+
+// Re-evaluate `slot` in FP64 (precision escalation of the mixed mode).  The
+// stored L-BFGS pairs and the CG direction were built from FP32 gradients
+// and their products with g would no longer match the FP64 gradient, so the
+// next direction starts again from -g.
 __device__ inline void escalate(Ctl* c, int slot) {
     c->escalated = 1;
     c->prec_now = P_FP64;
     c->phase = PH_REEVAL64;
+    c->steepest = 1;
+    lbfgs_clear(c);
     request_eval(c, PM_USE, slot, 0);
 }
 
@@ -246,23 +253,20 @@ __device__ inline void ls_after_trial(Ctl* c) {
 }
 
 // ------------------------------------------------------------- directions
-__device__ inline int gpos_s(int i) { return i; }
-__device__ inline int gpos_y(int i) { return kMaxM + i; }
+__device__ inline int ring_slot(const Ctl* c, int i) {
+    const int q = c->hist_head + i;
+    return q >= c->hist_m ? q - c->hist_m : q;
+}
+__device__ inline int gpos_s(int slot) { return slot; }
+__device__ inline int gpos_y(int slot) { return kMaxM + slot; }
 constexpr int kGposG = 2 * kMaxM;
 __device__ inline double& gram_at(Ctl* c, int a, int b) { return c->gram[a * kGramDim + b]; }
 
-// (G c)_k over the active basis
-__device__ inline double gram_mul(Ctl* c, const double* coef, int k) {
-    double s = 0.0;
-    const int n = c->hist_n;
-    for (int i = 0; i < n; ++i) s += gram_at(c, k, gpos_s(i)) * coef[gpos_s(i)];
-    for (int i = 0; i < n; ++i) s += gram_at(c, k, gpos_y(i)) * coef[gpos_y(i)];
-    s += gram_at(c, k, kGposG) * coef[kGposG];
-    return s;
-}
-
 __device__ inline void lbfgs_clear(Ctl* c) {
     c->hist_n = 0;
+    c->hist_head = 0;
+    c->hist_m = c->p.m;
+    c->lb_ready = 0;
     c->spare_s = V_S0;
     c->spare_y = V_Y0;
     c->spare_s_next = V_S0 + 1;
@@ -277,41 +281,13 @@ __device__ inline void set_steepest(Ctl* c) {
     c->steepest = 1;
 }
 
-// L-BFGS direction (Algorithm 3) in coefficient space.
-__device__ inline bool lbfgs_coefficients(Ctl* c) {
-    double coef[kGramDim];
-    for (int k = 0; k < kGramDim; ++k) coef[k] = 0.0;
-    coef[kGposG] = -1.0;
-    const int n = c->hist_n;
-    double alpha[kMaxM];
-    for (int i = n - 1; i >= 0; --i) {
-        alpha[i] = c->rho[i] * gram_mul(c, coef, gpos_s(i));
-        coef[gpos_y(i)] -= alpha[i];
-    }
-    const double gamma = gram_at(c, gpos_s(n - 1), gpos_y(n - 1)) / gram_at(c, gpos_y(n - 1), gpos_y(n - 1));
-    for (int k = 0; k < kGramDim; ++k) coef[k] *= gamma;
-    for (int i = 0; i < n; ++i) {
-        const double b = c->rho[i] * gram_mul(c, coef, gpos_y(i));
-        coef[gpos_s(i)] += alpha[i] - b;
-    }
-    const double gr = gram_mul(c, coef, kGposG);
-    if (!(gr < 0.0)) return false;
-    double nrm2 = 0.0;
-    for (int k = 0; k < kGramDim; ++k)
-        if (coef[k] != 0.0) nrm2 += coef[k] * gram_mul(c, coef, k);
-    int t = 0;
-    for (int i = 0; i < n; ++i) { c->term_vec[t] = c->hist_s[i]; c->term_coef[t++] = coef[gpos_s(i)]; }
-    for (int i = 0; i < n; ++i) { c->term_vec[t] = c->hist_y[i]; c->term_coef[t++] = coef[gpos_y(i)]; }
-    c->term_vec[t] = V_G0 + c->cur;
-    c->term_coef[t++] = coef[kGposG];
-    c->n_terms = t;
-    c->dir_scale = sqrt(nrm2);
-    c->steepest = 0;
-    return true;
-}
-
+// Starts the next iteration at the current point.  For L-BFGS with stored
+// pairs the direction's terms were filled by the workgroup step that ran
+// just before (lb_ready); they are used here or dropped.
 __device__ inline void begin_iteration(Ctl* c) {
     const MinParamsDev& p = c->p;
+    const int lb_ready = c->lb_ready;
+    c->lb_ready = 0;
     c->accept = 0;
     c->w = -1;
     c->ls_base = -1;
@@ -351,7 +327,9 @@ __device__ inline void begin_iteration(Ctl* c) {
         c->write_r = 1;
         break;
     case M_LBFGS:
-        if (c->hist_n == 0 || !lbfgs_coefficients(c)) {
+        if (c->hist_n > 0 && lb_ready == 1) {
+            c->steepest = 0;
+        } else {
             lbfgs_clear(c);
             set_steepest(c);
         }
@@ -401,6 +379,8 @@ __device__ void ls_success(Ctl* c, int slot, double h) {
     c->accept = 1;
     c->acc_new = slot;
     c->acc_old = c->ls_base;
+    // L-BFGS: the new pair's own products, then one row per stored pair
+    c->acc_rows = c->p.method == M_LBFGS ? c->hist_n + 1 : (c->p.method == M_CG ? 1 : 0);
     c->action = ACT_NONE;
 }
 
@@ -448,8 +428,10 @@ __device__ inline double cg_beta(int variant, double gg, double gngn, double gng
     return isfinite(b) ? b : 0.0;
 }
 
-// After the accept pass: update the method state and start the next iteration.
-__device__ inline void after_accept(Ctl* c, const double* dots) {
+// After the accept pass, first part: method state from the dot products.
+// Returns true when L-BFGS direction coefficients have to be computed (by the
+// whole workgroup) before accept_finish starts the next iteration.
+__device__ inline bool accept_update(Ctl* c, const double* dots) {
     const MinParamsDev& p = c->p;
     const int nw = c->acc_new, old = c->acc_old;
     switch (p.method) {
@@ -472,67 +454,53 @@ __device__ inline void after_accept(Ctl* c, const double* dots) {
     }
     case M_LBFGS: {
         // dots: [0] <s,y> [1] <y,y> [2] <s,s> [3] <g,s> [4] <g,y> [5] <g,g>,
-        // then per stored pair i: <s,S_i> <s,Y_i> <y,S_i> <y,Y_i> <g,S_i> <g,Y_i>
+        // then for the pair in slot q: dots[6 + 6q ..] = <s,S_q> <s,Y_q>
+        // <y,S_q> <y,Y_q> <g,S_q> <g,Y_q>
         const double sy = dots[0], yy = dots[1];
         const int n_old = c->hist_n;
+        const bool full = n_old == c->hist_m;
         if (sy > kEpsMach * yy) {
-            // drop the oldest pair if the memory is full
-            int first = 0;
-            if (n_old == p.m) first = 1;
-            const int n_new = n_old - first + 1;
-            double tmp_gs[kMaxM], tmp_gy[kMaxM];
-            // shift the stored part of the Gram matrix
-            for (int a2 = first; a2 < n_old; ++a2) {
-                for (int b2 = first; b2 < n_old; ++b2) {
-                    gram_at(c, gpos_s(a2 - first), gpos_s(b2 - first)) = gram_at(c, gpos_s(a2), gpos_s(b2));
-                    gram_at(c, gpos_s(a2 - first), gpos_y(b2 - first)) = gram_at(c, gpos_s(a2), gpos_y(b2));
-                    gram_at(c, gpos_y(a2 - first), gpos_s(b2 - first)) = gram_at(c, gpos_y(a2), gpos_s(b2));
-                    gram_at(c, gpos_y(a2 - first), gpos_y(b2 - first)) = gram_at(c, gpos_y(a2), gpos_y(b2));
-                }
-            }
-            const int drop_s = first ? c->hist_s[0] : -1, drop_y = first ? c->hist_y[0] : -1;
-            for (int i = first; i < n_old; ++i) {
-                c->hist_s[i - first] = c->hist_s[i];
-                c->hist_y[i - first] = c->hist_y[i];
-                c->rho[i - first] = c->rho[i];
-            }
-            const int q = n_new - 1;
-            c->hist_s[q] = c->spare_s;
-            c->hist_y[q] = c->spare_y;
-            c->rho[q] = 1.0 / sy;
-            for (int i = first; i < n_old; ++i) {
-                const double* d6 = dots + 6 + 6 * i;
-                const int r = i - first;
+            // the new pair takes the slot of the oldest one when the memory is full
+            const int q = full ? c->hist_head : ring_slot(c, n_old);
+            const int drop_s = c->hist_s[q], drop_y = c->hist_y[q];
+            for (int i = full ? 1 : 0; i < n_old; ++i) {
+                const int r = ring_slot(c, i);
+                const double* d6 = dots + 6 + 6 * r;
                 gram_at(c, gpos_s(q), gpos_s(r)) = gram_at(c, gpos_s(r), gpos_s(q)) = d6[0];
                 gram_at(c, gpos_s(q), gpos_y(r)) = gram_at(c, gpos_y(r), gpos_s(q)) = d6[1];
                 gram_at(c, gpos_y(q), gpos_s(r)) = gram_at(c, gpos_s(r), gpos_y(q)) = d6[2];
                 gram_at(c, gpos_y(q), gpos_y(r)) = gram_at(c, gpos_y(r), gpos_y(q)) = d6[3];
-                tmp_gs[r] = d6[4];
-                tmp_gy[r] = d6[5];
+                gram_at(c, kGposG, gpos_s(r)) = gram_at(c, gpos_s(r), kGposG) = d6[4];
+                gram_at(c, kGposG, gpos_y(r)) = gram_at(c, gpos_y(r), kGposG) = d6[5];
             }
             gram_at(c, gpos_s(q), gpos_s(q)) = dots[2];
             gram_at(c, gpos_s(q), gpos_y(q)) = gram_at(c, gpos_y(q), gpos_s(q)) = sy;
             gram_at(c, gpos_y(q), gpos_y(q)) = yy;
-            tmp_gs[q] = dots[3];
-            tmp_gy[q] = dots[4];
-            for (int r = 0; r < n_new; ++r) {
-                gram_at(c, kGposG, gpos_s(r)) = gram_at(c, gpos_s(r), kGposG) = tmp_gs[r];
-                gram_at(c, kGposG, gpos_y(r)) = gram_at(c, gpos_y(r), kGposG) = tmp_gy[r];
+            gram_at(c, kGposG, gpos_s(q)) = gram_at(c, gpos_s(q), kGposG) = dots[3];
+            gram_at(c, kGposG, gpos_y(q)) = gram_at(c, gpos_y(q), kGposG) = dots[4];
+            c->hist_s[q] = c->spare_s;
+            c->hist_y[q] = c->spare_y;
+            c->rho[q] = 1.0 / sy;
+            if (full) {
+                c->hist_head = c->hist_head + 1 == c->hist_m ? 0 : c->hist_head + 1;
+                c->spare_s = drop_s;
+                c->spare_y = drop_y;
+            } else {
+                c->hist_n = n_old + 1;
+                c->spare_s = c->spare_s_next++;
+                c->spare_y = c->spare_y_next++;
             }
-            c->hist_n = n_new;
-            c->spare_s = first ? drop_s : c->spare_s_next;
-            c->spare_y = first ? drop_y : c->spare_y_next;
-            if (!first) { c->spare_s_next += 1; c->spare_y_next += 1; }
         } else {
             for (int i = 0; i < n_old; ++i) {
-                const double* d6 = dots + 6 + 6 * i;
-                gram_at(c, kGposG, gpos_s(i)) = gram_at(c, gpos_s(i), kGposG) = d6[4];
-                gram_at(c, kGposG, gpos_y(i)) = gram_at(c, gpos_y(i), kGposG) = d6[5];
+                const int r = ring_slot(c, i);
+                const double* d6 = dots + 6 + 6 * r;
+                gram_at(c, kGposG, gpos_s(r)) = gram_at(c, gpos_s(r), kGposG) = d6[4];
+                gram_at(c, kGposG, gpos_y(r)) = gram_at(c, gpos_y(r), kGposG) = d6[5];
             }
         }
         gram_at(c, kGposG, kGposG) = dots[5];
         c->cur = nw;
-        break;
+        return c->hist_n > 0;
     }
     case M_FGM: {
         const double f_old = c->e[c->cur];
@@ -545,6 +513,13 @@ __device__ inline void after_accept(Ctl* c, const double* dots) {
         break;
     }
     }
+    return false;
+}
+
+// After the accept pass, second part: trace entry, iteration count, next
+// iteration.
+__device__ inline void accept_finish(Ctl* c) {
+    const int nw = c->acc_new;
     const int ti = c->iters - c->iters_base;
     if (c->trace_ptr && ti < c->trace_cap) {
         double* tr = c->trace_ptr + 3 * (size_t)ti;

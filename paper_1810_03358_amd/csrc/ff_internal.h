@@ -28,6 +28,9 @@ constexpr int kMaxDots = 6 * kMaxM + 8;    // dot products per vector pass
 constexpr int kMaxLsTrials = 8;
 constexpr int kBondedPerBlock = 256;  // bonded terms per workgroup
 constexpr int kTraceCap = 4096;       // per-iteration trace entries kept
+constexpr int kMaxChunk = 4096;       // j-tiles per pair workgroup, upper bound
+constexpr int kTicketGroups = 256;    // groups of the two-level reduction tickets
+constexpr int kTicketSlots = 1 + kTicketGroups;
 
 // Distances (A^2) below which the FP32 pair path first corrects the
 // displacement with the low halves of the double-single coordinates and,
@@ -93,9 +96,7 @@ struct Ctl {
     // ---- accept request for the vector pass after a successful line search
     int32_t accept;          // 1: k_accept has work this cycle
     int32_t acc_new, acc_old;
-    int32_t n_dots;
-    int32_t dot_a[kMaxDots], dot_b[kMaxDots];
-    double dot_val[kMaxDots];
+    int32_t acc_rows;        // rows of products of that pass (fixed while it runs)
 
     // ---- per-slot results
     double e[kNumSlots], ginf[kNumSlots], g2[kNumSlots];
@@ -118,12 +119,18 @@ struct Ctl {
     double theta_prev, fgm_theta, fgm_beta;  // FGM
     double accept_h;                         // step of the last accepted trial
     double cg_beta, r_norm2, r_dot_g_old, g_dot_g_old;   // CG
-    int32_t hist_n, hist_head;               // L-BFGS ring: positions 0..hist_n-1 oldest..newest
-    int32_t hist_s[kMaxM + 1], hist_y[kMaxM + 1];   // vector ids by ring position
+    // L-BFGS history: a ring of hist_m slots; stored pair i (0 = oldest,
+    // i < hist_n) sits in slot (hist_head + i) mod hist_m.  Everything below
+    // is indexed by slot, so storing a pair never moves the others.
+    int32_t hist_n, hist_head, hist_m;
+    int32_t hist_s[kMaxM + 1], hist_y[kMaxM + 1];   // vector ids by slot
     int32_t spare_s, spare_y;                        // vector ids for the next pair
     int32_t spare_s_next, spare_y_next;              // first never-used ids
-    double rho[kMaxM];
-    double gram[kGramDim * kGramDim];        // over positions [s_0..s_{n-1}, y_0..y_{n-1}, g]
+    double rho[kMaxM];                               // 1 / <s, y> by slot
+    // Gram matrix of {s of slot q at q, y of slot q at kMaxM + q, g at 2 kMaxM}
+    double gram[kGramDim * kGramDim];
+    int32_t lb_ready;        // direction coefficients for the next iteration:
+                             // 1 computed (terms filled), -1 not a descent direction, 0 none
     int32_t result_slot;
     // per-iteration trace (E, accepted h, evaluations so far); system 0 only
     double* trace_ptr;
@@ -131,8 +138,9 @@ struct Ctl {
     BatchState* batch;       // batch-wide counters
     int32_t n_atoms;         // atoms of this system
 
-    // ---- reduction tickets (last-block-done pattern)
-    uint32_t ticket_fin, ticket_acc, ticket_prep;
+    // ---- reduction tickets (two-level last-block-done pattern): [0] top
+    // level, [1 + g] group g
+    uint32_t ticket_fin[kTicketSlots], ticket_acc[kTicketSlots];
 };
 
 // ------------------------------------------------------- pair tile configs

@@ -43,21 +43,37 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], bool first_is_max,
     __syncthreads();
 }
 
-// Last-block-done over `count` workgroups: returns true in every thread of
-// the workgroup that finished last, which also resets the ticket counter.
-__device__ __forceinline__ bool last_block(uint32_t* ticket, uint32_t count) {
+// Last-block-done over `count` workgroups (idx = this one's index), with two
+// levels of tickets: workgroups form groups of G consecutive indices, and the
+// last workgroup of each group takes a ticket at the top level.  Atomics on
+// one address serialize across the chip (tens of ns each), so G ~ sqrt(count)
+// keeps the chain at about 2 sqrt(count) instead of count.  Returns true in
+// every thread of the workgroup that finished last; the counters reset
+// themselves.  Writes made before the call are visible to that workgroup.
+__device__ __forceinline__ bool last_block(uint32_t* tickets, uint32_t idx, uint32_t count) {
     __shared__ int is_last;
+    uint32_t g = (uint32_t)ceilf(sqrtf((float)count));
+    g = max(g, (count + kTicketGroups - 1) / kTicketGroups);
+    g = max(g, 1u);
+    const uint32_t ngroups = (count + g - 1) / g;
+    const uint32_t grp = idx / g;
+    const uint32_t gsize = min(g, count - grp * g);
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t t = atomicAdd(ticket, 1u);
-        is_last = (t == count - 1);
+        int last = 0;
+        if (atomicAdd(&tickets[1 + grp], 1u) == gsize - 1) {
+            atomicExch(&tickets[1 + grp], 0u);
+            __threadfence();
+            if (atomicAdd(&tickets[0], 1u) == ngroups - 1) {
+                atomicExch(&tickets[0], 0u);
+                last = 1;
+            }
+        }
+        is_last = last;
     }
     __syncthreads();
-    if (is_last) {
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(ticket, 0u);
-    }
+    if (is_last) __threadfence();
     return is_last != 0;
 }
 
@@ -76,36 +92,168 @@ __device__ __forceinline__ double block_sum_array(const double* p, int n, bool i
     return r;
 }
 
-// ------------------------------------------------------------------ finalize
-// Pair part of the gradient of `atom`: the i-side partials of every chunk of
-// its I-block, then the j-side partials of every unit that holds its j-tile,
-// in a fixed order.  T is the storage type of the partials (FP32 mode: float).
-template <typename T>
-__device__ __forceinline__ void gather_pair(const Args& a, int row0, int atom, double& gx, double& gy, double& gz) {
-    const Layout& L = a.L;
-    const int row = atom / L.block, il = atom - row * L.block;
-    const int t = atom / kTile, jl = atom - t * kTile;
-    const RowInfo* R = at<RowInfo>(a.ws, L.off_rows);
-    const T* Pi = at<T>(a.ws, L.off_pi);
-    const T* Pj = at<T>(a.ws, L.off_pj);
-    const RowInfo ri = R[row];
-    for (int ch = ri.chunk_start; ch < ri.chunk_start + ri.n_chunks; ++ch) {
-        const T* p = Pi + ((size_t)ch * L.block + il) * 3;
-        gx += (double)p[0]; gy += (double)p[1]; gz += (double)p[2];
+// -------------------------------------------------------- L-BFGS direction
+// Coefficients of the L-BFGS direction r = -H g (Algorithm 3) in the basis
+// {s_0..s_{n-1}, y_0..y_{n-1}, g} of the stored pairs (oldest first) and the
+// current gradient, from the Gram matrix of that basis: the two loops of the
+// recursion act on coefficient vectors, every inner product becomes a row of
+// the Gram matrix times the coefficients.  The workgroup copies the active
+// (2n+1)^2 block into LDS; the first wavefront runs the loops, one wavefront
+// sum per inner product (lane k holds coefficients k and k + 64).  On a
+// descent direction (<g, r> < 0) the terms of r and |r| are written to the
+// control block and lb_ready = 1, otherwise lb_ready = -1.  Every thread of
+// the workgroup calls this; hist_n >= 1.
+__device__ void lbfgs_direction_block(Ctl* c) {
+    __shared__ double gs[kGramDim * kGramDim];
+    __shared__ double cs[kGramDim];
+    __shared__ int pos[kGramDim];
+    const int n = c->hist_n;
+    const int nb = 2 * n + 1;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x)
+        pos[k] = k < n ? gpos_s(ring_slot(c, k)) : (k < 2 * n ? gpos_y(ring_slot(c, k - n)) : kGposG);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, q = e - r * nb;
+        gs[e] = c->gram[pos[r] * kGramDim + pos[q]];
     }
-    for (int r = row0; r <= row; ++r) {
-        const RowInfo rr = R[r];
-        const T* p = Pj + ((size_t)(rr.unit_start + t - rr.t0) * kTile + jl) * 3;
-        gx += (double)p[0]; gy += (double)p[1]; gz += (double)p[2];
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int l = threadIdx.x, l2 = l + 64;
+    double c0 = l == 2 * n ? -1.0 : 0.0;     // coefficient of basis element l
+    double c1 = l2 == 2 * n ? -1.0 : 0.0;    // ... and of l + 64
+    const double rho_l = l < n ? c->rho[ring_slot(c, l)] : 0.0;
+    auto row_times_coef = [&](int r) {
+        double v = 0.0;
+        if (l < nb) v = gs[r * nb + l] * c0;
+        if (l2 < nb) v += gs[r * nb + l2] * c1;
+        return wave_sum(v);
+    };
+    double alpha_l = 0.0;
+    for (int i = n - 1; i >= 0; --i) {             // newest to oldest
+        const double a = __shfl(rho_l, i, 64) * row_times_coef(i);
+        if (l == i) alpha_l = a;
+        if (l == n + i) c0 -= a;
+        if (l2 == n + i) c1 -= a;
+    }
+    const double gamma = gs[(n - 1) * nb + (2 * n - 1)] / gs[(2 * n - 1) * nb + (2 * n - 1)];
+    c0 *= gamma;
+    c1 *= gamma;
+    for (int i = 0; i < n; ++i) {                  // oldest to newest
+        const double b = __shfl(rho_l, i, 64) * row_times_coef(n + i);
+        const double ai = __shfl(alpha_l, i, 64);
+        if (l == i) c0 += ai - b;
+    }
+    const double gr = row_times_coef(2 * n);       // <g, r>
+    if (l < nb) cs[l] = c0;
+    if (l2 < nb) cs[l2] = c1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // |r|^2 = c^T G c
+    double part = 0.0;
+    if (l < nb && c0 != 0.0) {
+        double t = 0.0;
+        for (int q = 0; q < nb; ++q) t += gs[l * nb + q] * cs[q];
+        part = c0 * t;
+    }
+    if (l2 < nb && c1 != 0.0) {
+        double t = 0.0;
+        for (int q = 0; q < nb; ++q) t += gs[l2 * nb + q] * cs[q];
+        part += c1 * t;
+    }
+    const double nrm2 = wave_sum(part);
+    const bool ok = gr < 0.0 && nrm2 > 0.0 && isfinite(nrm2);
+    if (ok) {
+        auto term = [&](int k, double coef) {
+            c->term_vec[k] = k < n ? c->hist_s[ring_slot(c, k)]
+                           : (k < 2 * n ? c->hist_y[ring_slot(c, k - n)] : V_G0 + c->cur);
+            c->term_coef[k] = coef;
+        };
+        if (l < nb) term(l, c0);
+        if (l2 < nb) term(l2, c1);
+    }
+    if (l == 0) {
+        if (ok) {
+            c->n_terms = nb;
+            c->dir_scale = sqrt(nrm2);
+        }
+        c->lb_ready = ok ? 1 : -1;
     }
 }
 
-// One thread per atom: gradient = sum of the pair partials of its I-block
-// (all chunks of its row), of the j partials of every unit holding it, and
-// of its bonded-term slots.  Then |g|_inf, |g|^2, optionally <g_base, d>, and
-// E = sum of the pair-workgroup and bonded-block energies.
-// Grid: (largest per-system block count, 1, systems); atoms are local to the
-// system, reductions and the decision step are per system.
+// ------------------------------------------------------------------ finalize
+// Pair partials of one 64-atom tile t of I-block `row`, summed over its
+// partial rows in a fixed order.  The tile's rows are the i-side partials
+// of every chunk of its I-block, then the j-side partials of every unit that
+// holds tile t (I-blocks row0..row).  Each row is 192 contiguous values
+// (64 atoms x xyz); wavefront w of the workgroup sums rows w, w+4, ... (lane
+// l holds values l, l+64, l+128), the four wavefront sums are then added in
+// order.  T is the storage type of the partials (FP32 mode: float).
+template <typename T>
+__device__ __forceinline__ void gather_tile(const Args& a, const SysInfo& si, int row, int t,
+                                            double* tot /* LDS [192] */) {
+    __shared__ double part[kFinBlock / 64][3 * kTile];
+    const Layout& L = a.L;
+    const RowInfo* R = at<RowInfo>(a.ws, L.off_rows);
+    const T* Pi = at<T>(a.ws, L.off_pi);
+    const T* Pj = at<T>(a.ws, L.off_pj);
+    const int row0 = si.row0;
+    const RowInfo ri = R[row];
+    const int il0 = t * kTile - row * L.block;
+    const int n_i = ri.n_chunks, nseg = n_i + row - row0 + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kFinBlock / 64;
+    // Units of a system are numbered row by row, local row r holding tiles
+    // r*B/64 .. nt-1, so the unit of (row r, tile tl) has a closed form and
+    // the addresses need no table loads.
+    const long long u0 = R[row0].unit_start;
+    const long long nt = si.np / kTile, b64 = L.block / kTile;
+    const long long tl = t - si.aoff / kTile;
+    auto seg = [&](int sg) -> const T* {
+        if (sg < n_i) return Pi + ((size_t)(ri.chunk_start + sg) * L.block + il0) * 3;
+        const long long r = sg - n_i;
+        const long long unit = u0 + r * nt - b64 * r * (r - 1) / 2 + (tl - r * b64);
+        return Pj + (size_t)unit * (3 * kTile);
+    };
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    int sg = wave;
+    // four rows in flight per wavefront, added in row order
+    for (; sg + 3 * kWaves < nseg; sg += 4 * kWaves) {
+        const T* p0 = seg(sg);
+        const T* p1 = seg(sg + kWaves);
+        const T* p2 = seg(sg + 2 * kWaves);
+        const T* p3 = seg(sg + 3 * kWaves);
+        const T v00 = p0[lane], v01 = p0[lane + 64], v02 = p0[lane + 128];
+        const T v10 = p1[lane], v11 = p1[lane + 64], v12 = p1[lane + 128];
+        const T v20 = p2[lane], v21 = p2[lane + 64], v22 = p2[lane + 128];
+        const T v30 = p3[lane], v31 = p3[lane + 64], v32 = p3[lane + 128];
+        a0 += (double)v00; a1 += (double)v01; a2 += (double)v02;
+        a0 += (double)v10; a1 += (double)v11; a2 += (double)v12;
+        a0 += (double)v20; a1 += (double)v21; a2 += (double)v22;
+        a0 += (double)v30; a1 += (double)v31; a2 += (double)v32;
+    }
+    for (; sg < nseg; sg += kWaves) {
+        const T* p0 = seg(sg);
+        a0 += (double)p0[lane]; a1 += (double)p0[lane + 64]; a2 += (double)p0[lane + 128];
+    }
+    part[wave][lane] = a0;
+    part[wave][lane + 64] = a1;
+    part[wave][lane + 128] = a2;
+    __syncthreads();
+    if (threadIdx.x < 3 * kTile) {
+        double v = part[0][threadIdx.x];
+        for (int w = 1; w < kWaves; ++w) v += part[w][threadIdx.x];
+        tot[threadIdx.x] = v;
+    }
+    __syncthreads();
+}
+
+// One workgroup per 64-atom tile of a system: gradient = pair partials of
+// the tile (gather_tile) + the bonded-term slots of each atom (staged through
+// LDS, added in slot order).  Then |g|_inf, |g|^2, optionally <g_base, d>,
+// and in the last workgroup of the system E = sum of the pair-workgroup and
+// bonded-block energies.  Grid: (largest per-system tile count, 1, systems);
+// reductions and the decision step are per system.
 __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     const Layout& L = a.L;
     const int sys = blockIdx.z;
@@ -115,59 +263,99 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     if (!a.direct && (c->action != ACT_EVAL || c->target < 0 || c->target >= kNumSlots)) return;
     double* G = a.direct ? (a.g_out ? a.g_out + 3 * (size_t)si.uoff : nullptr) : vec(a, V_G0 + c->target, si);
     const bool want_slope = !a.direct && c->want_slope;
-    const int atom = blockIdx.x * kFinBlock + threadIdx.x;
+    const int t = si.aoff / kTile + blockIdx.x;          // global tile
+    const int row = t * kTile / L.block;                 // its I-block
+    __shared__ double tot[3 * kTile];
+    __shared__ double fbv[kFinBlock][3];
+    const bool p32 = a.direct ? a.direct_prec == 1 : c->prec == 1;
+    if (p32) gather_tile<float>(a, si, row, t, tot);
+    else gather_tile<double>(a, si, row, t, tot);
+    // bonded-term slots of the tile's atoms: contiguous in the incidence list
+    const int* inc0 = at<int>(a.ws, L.off_inc_start);
+    const int* inc = at<int>(a.ws, L.off_inc);
+    const double* FB = at<double>(a.ws, L.off_fb);
+    const int ga = t * kTile + (int)threadIdx.x;         // global padded atom (threads < 64)
+    const int k_lo = inc0[t * kTile], k_hi = inc0[t * kTile + kTile];
+    int my_lo = 0, my_hi = 0;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    if (atom < si.n) {
-        const int ga = si.aoff + atom;      // global padded atom
-        const bool p32 = a.direct ? a.direct_prec == 1 : c->prec == 1;
-        if (p32) gather_pair<float>(a, si.row0, ga, gx, gy, gz);
-        else gather_pair<double>(a, si.row0, ga, gx, gy, gz);
-        const int* inc0 = at<int>(a.ws, L.off_inc_start);
-        const int* inc = at<int>(a.ws, L.off_inc);
-        const double* FB = at<double>(a.ws, L.off_fb);
-        for (int k = inc0[ga]; k < inc0[ga + 1]; ++k) {
-            const double* p = FB + 3 * (size_t)inc[k];
-            gx += p[0]; gy += p[1]; gz += p[2];
-        }
-        if (G) { G[3 * (size_t)atom] = gx; G[3 * (size_t)atom + 1] = gy; G[3 * (size_t)atom + 2] = gz; }
+    if (threadIdx.x < kTile) {
+        my_lo = inc0[ga];
+        my_hi = inc0[ga + 1];
+        gx = tot[3 * threadIdx.x];
+        gy = tot[3 * threadIdx.x + 1];
+        gz = tot[3 * threadIdx.x + 2];
     }
-    double v[3];
+    for (int base = k_lo; base < k_hi; base += kFinBlock) {
+        const int k = base + (int)threadIdx.x;
+        if (k < k_hi) {
+            const double* p = FB + 3 * (size_t)inc[k];
+            fbv[threadIdx.x][0] = p[0];
+            fbv[threadIdx.x][1] = p[1];
+            fbv[threadIdx.x][2] = p[2];
+        }
+        __syncthreads();
+        if (threadIdx.x < kTile) {
+            const int e = min(my_hi, base + kFinBlock);
+            for (int q = max(my_lo, base); q < e; ++q) {
+                gx += fbv[q - base][0]; gy += fbv[q - base][1]; gz += fbv[q - base][2];
+            }
+        }
+        __syncthreads();
+    }
+    const int atom = blockIdx.x * kTile + (int)threadIdx.x;   // local atom
+    const bool real = threadIdx.x < kTile && atom < si.n;
+    if (!real) gx = gy = gz = 0.0;
+    if (real && G) { G[3 * (size_t)atom] = gx; G[3 * (size_t)atom + 1] = gy; G[3 * (size_t)atom + 2] = gz; }
+    double v[4];
     v[0] = fmax(fabs(gx), fmax(fabs(gy), fabs(gz)));
     if (isnan(gx) || isnan(gy) || isnan(gz)) v[0] = __builtin_inf();
     v[1] = gx * gx + gy * gy + gz * gz;
     v[2] = 0.0;
-    if (want_slope && atom < si.n) {
+    if (want_slope && real) {
         const double* gb = vec(a, V_G0 + c->base, si);
         const double* d = vec(a, V_D, si);
         const size_t o = 3 * (size_t)atom;
         v[2] = gb[o] * d[o] + gb[o + 1] * d[o + 1] + gb[o + 2] * d[o + 2];
     }
-    double* red = at<double>(a.ws, L.off_red) + si.red0;
-    double tot[3];
-    block_reduce<3>(v, true, tot);
-    if (threadIdx.x == 0) { red[3 * blockIdx.x] = tot[0]; red[3 * blockIdx.x + 1] = tot[1]; red[3 * blockIdx.x + 2] = tot[2]; }
-    if (!last_block(&c->ticket_fin, si.fin_blocks)) return;
-    // ---- last workgroup of this system: totals in a fixed order
-    double w[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < si.fin_blocks; b += kFinBlock) {
-        w[0] = fmax(w[0], red[3 * b]);
-        w[1] += red[3 * b + 1];
-        w[2] += red[3 * b + 2];
+    // this workgroup's share of the pair-workgroup and bonded-block energies
+    {
+        const int nb = si.fin_blocks, b = blockIdx.x;
+        const double* ep = at<double>(a.ws, L.off_ep) + si.chunk0;
+        const double* eb = at<double>(a.ws, L.off_eb) + si.eb0;
+        const int p0 = (int)((long long)si.n_chunks * b / nb), p1 = (int)((long long)si.n_chunks * (b + 1) / nb);
+        const int q0 = (int)((long long)si.bonded_blocks * b / nb), q1 = (int)((long long)si.bonded_blocks * (b + 1) / nb);
+        double e = 0.0;
+        for (int k = p0 + (int)threadIdx.x; k < p1; k += kFinBlock) e += ep[k];
+        for (int k = q0 + (int)threadIdx.x; k < q1; k += kFinBlock) e += eb[k];
+        v[3] = e;
     }
-    double gt[3];
-    block_reduce<3>(w, true, gt);
-    const double e_pair = block_sum_array(at<double>(a.ws, L.off_ep) + si.chunk0, si.n_chunks);
-    const double e_bond = block_sum_array(at<double>(a.ws, L.off_eb) + si.eb0, si.bonded_blocks);
+    double* red = at<double>(a.ws, L.off_red) + si.red0;
+    double tr[4];
+    block_reduce<4>(v, true, tr);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) red[4 * blockIdx.x + k] = tr[k];
+    if (!last_block(c->ticket_fin, blockIdx.x, si.fin_blocks)) return;
+    // ---- last workgroup of this system: totals in a fixed order
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int b = threadIdx.x; b < si.fin_blocks; b += kFinBlock) {
+        w[0] = fmax(w[0], red[4 * b]);
+        w[1] += red[4 * b + 1];
+        w[2] += red[4 * b + 2];
+        w[3] += red[4 * b + 3];
+    }
+    double gt[4];
+    block_reduce<4>(w, true, gt);
     if (threadIdx.x != 0) return;
-    const double E = e_pair + e_bond;
+    const double E = gt[3];
     if (a.direct) {
         if (a.e_out) a.e_out[sys] = E;
         return;
     }
-    const int t = c->target;
-    c->e[t] = E;
-    c->ginf[t] = gt[0];
-    c->g2[t] = gt[1];
+    const int tg = c->target;
+    c->e[tg] = E;
+    c->ginf[tg] = gt[0];
+    c->g2[tg] = gt[1];
     if (want_slope) c->slope = gt[2];
     after_eval(c);
 }
@@ -213,9 +401,10 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
 //  CG:     <g_new, g_old>, <g_new, r_old>, <r_old, g_old>
 //  L-BFGS: s = x_new - x_old and y = g_new - g_old (written to the spare
 //          history vectors), <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for
-//          every stored pair i, <s,S_i> <s,Y_i> <y,S_i> <y,Y_i> <g,S_i> <g,Y_i>.
+//          the pair in every occupied history slot q, <s,S_q> <s,Y_q>
+//          <y,S_q> <y,Y_q> <g,S_q> <g,Y_q>.
 // Grid: (accept_bx, kMaxM + 1).  Row 0 computes the first group of six, row
-// r >= 1 the six products with stored pair r-1 (s and y are recomputed from
+// r >= 1 the six products with the pair in slot r-1 (s and y are recomputed from
 // the point vectors in every row, with the same arithmetic); each block
 // strides over its share of the 3N elements and reduces once.  The last
 // block sums the per-block partials of every dot in block order.
@@ -227,8 +416,11 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
     const int n3 = 3 * si.n;
     const int method = c->p.method;
     const int row = blockIdx.y;
-    const int nh = method == M_LBFGS ? c->hist_n : 0;
-    const bool active = (method == M_LBFGS && row <= nh) || (method == M_CG && row == 0);
+    // acc_rows is fixed while this pass runs (the last workgroup changes
+    // hist_n, and a workgroup without work may start after that)
+    const int rows = c->acc_rows;
+    const int nh = method == M_LBFGS ? rows - 1 : 0;
+    const bool active = row < rows;
     double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     const int nbx = gridDim.x;
     if (active) {
@@ -274,52 +466,63 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
         if (threadIdx.x == 0)
             for (int k = 0; k < 6; ++k) red[((size_t)row * nbx + blockIdx.x) * 6 + k] = tot[k];
     }
-    // every block takes a ticket; the last one finishes the reduction
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t t = atomicAdd(&c->ticket_acc, 1u);
-        is_last = (t == gridDim.x * gridDim.y - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    // the workgroups with work take tickets (GD and FGM have no products:
+    // workgroup (0, 0) alone runs the decision); the last one reduces
+    if (rows == 0 ? (row != 0 || blockIdx.x != 0) : !active) return;
+    const uint32_t count = rows == 0 ? 1u : (uint32_t)(nbx * rows);
+    if (!last_block(c->ticket_acc, (uint32_t)(row * nbx + (int)blockIdx.x), count)) return;
     __shared__ double dots[kMaxDots];
     const int nd = method == M_LBFGS ? 6 * (nh + 1) : (method == M_CG ? 3 : 0);
     for (int k = threadIdx.x; k < nd; k += kFinBlock) {
         const int r = k / 6, q = k - 6 * r;
         double acc = 0.0;
+#pragma unroll 16
         for (int b = 0; b < nbx; ++b) acc += red[((size_t)r * nbx + b) * 6 + q];
         dots[k] = acc;
     }
+    __shared__ int need_dir;
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    c->ticket_acc = 0u;
-    after_accept(c, dots);
+    if (threadIdx.x == 0) need_dir = accept_update(c, dots) ? 1 : 0;
+    __syncthreads();
+    if (need_dir) lbfgs_direction_block(c);
+    __syncthreads();
+    if (threadIdx.x == 0) accept_finish(c);
 }
 
 // ---------------------------------------------------------------------- kick
 // Starts (or resumes) a minimization: one thread sets up the control block.
 // One workgroup per system (system 0 keeps the per-iteration trace).
 __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int trace_cap) {
-    if (threadIdx.x != 0) return;
     const int sys = blockIdx.x;
     Ctl* c = ctl_at(a, sys);
+    if (resume) {
+        // continue where the previous call stopped; the L-BFGS direction is
+        // recomputed from the stored pairs exactly as after an accept
+        __shared__ int need_dir;
+        if (threadIdx.x == 0) {
+            c->batch = at<BatchState>(a.ws, a.L.off_batch);
+            c->n_atoms = sys_info(a)[sys].n;
+            const bool same_memory = c->p.method == M_LBFGS && p.method == M_LBFGS && c->hist_m == p.m;
+            c->p = p;
+            if (!same_memory) lbfgs_clear(c);
+            c->done = 0;
+            c->iters_limit = c->iters + p.max_iter;
+            c->trace_ptr = sys == 0 ? trace : nullptr;
+            c->trace_cap = trace_cap;
+            c->n_trace = 0;
+            c->iters_base = c->iters;
+            need_dir = p.method == M_LBFGS && c->hist_n > 0;
+        }
+        __syncthreads();
+        if (need_dir) lbfgs_direction_block(c);
+        __syncthreads();
+        if (threadIdx.x == 0) begin_iteration(c);
+        return;
+    }
+    if (threadIdx.x != 0) return;
     if (sys != 0) trace = nullptr;
     c->batch = at<BatchState>(a.ws, a.L.off_batch);
     c->n_atoms = sys_info(a)[sys].n;
-    if (resume) {
-        c->p = p;
-        c->done = 0;
-        c->iters_limit = c->iters + p.max_iter;
-        c->trace_ptr = trace;
-        c->trace_cap = trace_cap;
-        c->n_trace = 0;
-        c->iters_base = c->iters;
-        begin_iteration(c);
-        return;
-    }
     c->p = p;
     c->phase = PH_START;
     c->done = 0;
@@ -349,7 +552,7 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
     c->trace_ptr = trace;
     c->trace_cap = trace_cap;
     c->n_trace = 0;
-    c->ticket_fin = c->ticket_acc = c->ticket_prep = 0u;
+    for (int k = 0; k < kTicketSlots; ++k) c->ticket_fin[k] = c->ticket_acc[k] = 0u;
     request_eval(c, PM_USE, 0, 0);
 }
 
@@ -366,7 +569,7 @@ __global__ void k_reset_ctl(Args a) {
     if (threadIdx.x != 0) return;
     Ctl* c = ctl_at(a, blockIdx.x);
     c->batch = nullptr;
-    c->ticket_fin = c->ticket_acc = c->ticket_prep = 0u;
+    for (int k = 0; k < kTicketSlots; ++k) c->ticket_fin[k] = c->ticket_acc[k] = 0u;
     c->action = ACT_NONE;
     c->accept = 0;
     c->done = 1;

@@ -115,3 +115,34 @@ def test_batch_workspace_and_validation():
     ctx = C.c_void_p()
     st = lib.ff_create_batch(arr2, 2, C.c_void_p(256), 1 << 40, 10, None, C.byref(ctx))
     assert st == ff.FF_ERR_ARG and "system 1" in N.last_error()
+
+
+def test_tile_configs_and_tiled_workspace():
+    cfgs = ff.tile_configs()
+    assert len(cfgs) >= 4
+    for block, w32, i32, w64, i64 in cfgs:
+        assert block == 64 * w32 * i32 == 64 * w64 * i64
+    lib = N.load()
+    s = chain_system(700, 3)
+    arr = (N.FFSystem * 1)(ff.HostSystem(s).c)
+    for k in range(len(cfgs)):
+        for chunk in (1, 4, 16):
+            b = lib.ff_workspace_bytes_tiled(arr, 1, 10, k, chunk)
+            assert b > 0 and b % 256 == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, len(cfgs), 4) == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 0) == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 5000) == 0
+    need = lib.ff_autotune_workspace_bytes(arr, 1)
+    assert need >= max(lib.ff_workspace_bytes_tiled(arr, 1, 0, k, c) for k in range(len(cfgs)) for c in (1, 16))
+    assert lib.ff_tile_config_info(len(cfgs), None, None, None, None, None) == ff.FF_ERR_ARG
+
+
+def test_create_tiled_rejects_bad_tiling_before_touching_the_device():
+    lib = N.load()
+    s = chain_system(100, 3)
+    arr = (N.FFSystem * 1)(ff.HostSystem(s).c)
+    ctx = C.c_void_p()
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, -1, 4, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 99, 4, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 0, 0, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1024, 10, 0, 4, None, C.byref(ctx)) == ff.FF_ERR_WORKSPACE
