@@ -103,7 +103,8 @@ def batch_bench(args):
         x = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = ctx.minimize(x, "lbfgs", m=10, tol=1e-3, max_iter=2000, precision=args.precision, stream=stream)
+        res = ctx.minimize(x, "lbfgs", m=10, tol=1e-3, max_iter=args.batch_iters, precision=args.precision,
+                           stream=stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     evals = sum(r["evals"] for r in res)
@@ -120,7 +121,8 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": "batch256", "systems": len(systems), "atoms": int(sum(sizes)),
                    "sizes": "log-uniform [200, 4000], seeds 100-355", "pairs_per_eval_all_systems": pairs,
-                   "method": "L-BFGS m=10, LS_PAR, tol 1e-3, max_iter 2000", "tiling": list(tiling)},
+                   "method": f"L-BFGS m=10, LS_PAR, tol 1e-3, max_iter {args.batch_iters}",
+                   "tiling": list(tiling)},
         "wall_s": wall,
         "converged": int(conv),
         "iters_median": float(np.median(iters)), "iters_max": int(iters.max()),
@@ -140,6 +142,7 @@ def main():
     ap.add_argument("--workload", default="chain50k", choices=["chain512", "chain10k", "chain50k", "batch256"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-iters", type=int, default=2000, help="batch256: iteration limit per system")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")

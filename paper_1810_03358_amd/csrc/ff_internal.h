@@ -29,8 +29,6 @@ constexpr int kMaxLsTrials = 8;
 constexpr int kBondedPerBlock = 256;  // bonded terms per workgroup
 constexpr int kTraceCap = 4096;       // per-iteration trace entries kept
 constexpr int kMaxChunk = 4096;       // j-tiles per pair workgroup, upper bound
-constexpr int kTicketGroups = 256;    // groups of the two-level reduction tickets
-constexpr int kTicketSlots = 1 + kTicketGroups;
 
 // Distances (A^2) below which the FP32 pair path first corrects the
 // displacement with the low halves of the double-single coordinates and,
@@ -138,9 +136,6 @@ struct Ctl {
     BatchState* batch;       // batch-wide counters
     int32_t n_atoms;         // atoms of this system
 
-    // ---- reduction tickets (two-level last-block-done pattern): [0] top
-    // level, [1 + g] group g
-    uint32_t ticket_fin[kTicketSlots], ticket_acc[kTicketSlots];
 };
 
 // ------------------------------------------------------- pair tile configs

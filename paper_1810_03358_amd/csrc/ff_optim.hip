@@ -1,8 +1,11 @@
 // Per-evaluation finalize (gradient gather, norms, energy total) and the
 // optimizer's vector passes: trial point / direction construction and the
-// accept pass (history vectors and their dot products).  Each kernel closes
-// with a deterministic fixed-order reduction in its last workgroup
-// (last-block-done ticket), which then runs the decision step.
+// accept pass (history vectors and their dot products).  A pass that ends in
+// a reduction writes per-workgroup partials; a second kernel with one
+// workgroup per system sums them in a fixed order and runs the decision step.
+// (No workgroup waits for others inside a kernel: on this GPU each XCD has its
+// own L2, and the device-scope fence such a handshake needs writes the L2
+// back every time; the kernel boundary does that once.)
 #include "ff_decide.h"
 
 namespace ff {
@@ -41,40 +44,6 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], bool first_is_max,
         }
     }
     __syncthreads();
-}
-
-// Last-block-done over `count` workgroups (idx = this one's index), with two
-// levels of tickets: workgroups form groups of G consecutive indices, and the
-// last workgroup of each group takes a ticket at the top level.  Atomics on
-// one address serialize across the chip (tens of ns each), so G ~ sqrt(count)
-// keeps the chain at about 2 sqrt(count) instead of count.  Returns true in
-// every thread of the workgroup that finished last; the counters reset
-// themselves.  Writes made before the call are visible to that workgroup.
-__device__ __forceinline__ bool last_block(uint32_t* tickets, uint32_t idx, uint32_t count) {
-    __shared__ int is_last;
-    uint32_t g = (uint32_t)ceilf(sqrtf((float)count));
-    g = max(g, (count + kTicketGroups - 1) / kTicketGroups);
-    g = max(g, 1u);
-    const uint32_t ngroups = (count + g - 1) / g;
-    const uint32_t grp = idx / g;
-    const uint32_t gsize = min(g, count - grp * g);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int last = 0;
-        if (atomicAdd(&tickets[1 + grp], 1u) == gsize - 1) {
-            atomicExch(&tickets[1 + grp], 0u);
-            __threadfence();
-            if (atomicAdd(&tickets[0], 1u) == ngroups - 1) {
-                atomicExch(&tickets[0], 0u);
-                last = 1;
-            }
-        }
-        is_last = last;
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
 }
 
 // Fixed-order sum of n doubles by one 256-thread block (result in thread 0).
@@ -250,10 +219,10 @@ __device__ __forceinline__ void gather_tile(const Args& a, const SysInfo& si, in
 
 // One workgroup per 64-atom tile of a system: gradient = pair partials of
 // the tile (gather_tile) + the bonded-term slots of each atom (staged through
-// LDS, added in slot order).  Then |g|_inf, |g|^2, optionally <g_base, d>,
-// and in the last workgroup of the system E = sum of the pair-workgroup and
-// bonded-block energies.  Grid: (largest per-system tile count, 1, systems);
-// reductions and the decision step are per system.
+// LDS, added in slot order).  Per-workgroup partials: max |g|, |g|^2,
+// optionally <g_base, d>, and a share of the pair-workgroup and bonded-block
+// energies (k_fin_reduce adds them up).  Grid: (largest per-system tile
+// count, 1, systems).
 __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     const Layout& L = a.L;
     const int sys = blockIdx.z;
@@ -334,8 +303,18 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     block_reduce<4>(v, true, tr);
     if (threadIdx.x == 0)
         for (int k = 0; k < 4; ++k) red[4 * blockIdx.x + k] = tr[k];
-    if (!last_block(c->ticket_fin, blockIdx.x, si.fin_blocks)) return;
-    // ---- last workgroup of this system: totals in a fixed order
+}
+
+// Totals of one system's finalize partials in a fixed order, then E, the
+// norms and the decision step (ff_energy_grad: the energy only).
+// Grid: (systems).
+__global__ void __launch_bounds__(kFinBlock) k_fin_reduce(Args a) {
+    const int sys = blockIdx.x;
+    const SysInfo si = sys_info(a)[sys];
+    Ctl* c = ctl_at(a, sys);
+    if (!a.direct && (c->action != ACT_EVAL || c->target < 0 || c->target >= kNumSlots)) return;
+    const bool want_slope = !a.direct && c->want_slope;
+    const double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     double w[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int b = threadIdx.x; b < si.fin_blocks; b += kFinBlock) {
@@ -403,11 +382,11 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
 //          history vectors), <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for
 //          the pair in every occupied history slot q, <s,S_q> <s,Y_q>
 //          <y,S_q> <y,Y_q> <g,S_q> <g,Y_q>.
-// Grid: (accept_bx, kMaxM + 1).  Row 0 computes the first group of six, row
-// r >= 1 the six products with the pair in slot r-1 (s and y are recomputed from
-// the point vectors in every row, with the same arithmetic); each block
-// strides over its share of the 3N elements and reduces once.  The last
-// block sums the per-block partials of every dot in block order.
+// Grid: (accept_bx, kMaxM + 1, systems).  Row 0 computes the first group of
+// six, row r >= 1 the six products with the pair in slot r-1 (s and y are
+// recomputed from the point vectors in every row, with the same arithmetic);
+// each workgroup strides over its share of the 3N elements and writes one
+// partial per product (k_accept_reduce adds them up in workgroup order).
 __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
     const int sys = blockIdx.z;
     const SysInfo si = sys_info(a)[sys];
@@ -466,13 +445,22 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
         if (threadIdx.x == 0)
             for (int k = 0; k < 6; ++k) red[((size_t)row * nbx + blockIdx.x) * 6 + k] = tot[k];
     }
-    // the workgroups with work take tickets (GD and FGM have no products:
-    // workgroup (0, 0) alone runs the decision); the last one reduces
-    if (rows == 0 ? (row != 0 || blockIdx.x != 0) : !active) return;
-    const uint32_t count = rows == 0 ? 1u : (uint32_t)(nbx * rows);
-    if (!last_block(c->ticket_acc, (uint32_t)(row * nbx + (int)blockIdx.x), count)) return;
+}
+
+// Sums the accept pass's per-workgroup products in a fixed order, then the
+// method update and the next iteration (L-BFGS: coefficients of the next
+// direction computed by the workgroup first).  Grid: (systems).
+__global__ void __launch_bounds__(kFinBlock) k_accept_reduce(Args a) {
+    const int sys = blockIdx.x;
+    const SysInfo si = sys_info(a)[sys];
+    Ctl* c = ctl_at(a, sys);
+    if (!c->accept) return;
+    const int method = c->p.method;
+    const int rows = c->acc_rows;
+    const int nbx = a.L.accept_bx;
+    const double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     __shared__ double dots[kMaxDots];
-    const int nd = method == M_LBFGS ? 6 * (nh + 1) : (method == M_CG ? 3 : 0);
+    const int nd = method == M_LBFGS ? 6 * rows : (method == M_CG ? 3 : 0);
     for (int k = threadIdx.x; k < nd; k += kFinBlock) {
         const int r = k / 6, q = k - 6 * r;
         double acc = 0.0;
@@ -552,7 +540,6 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
     c->trace_ptr = trace;
     c->trace_cap = trace_cap;
     c->n_trace = 0;
-    for (int k = 0; k < kTicketSlots; ++k) c->ticket_fin[k] = c->ticket_acc[k] = 0u;
     request_eval(c, PM_USE, 0, 0);
 }
 
@@ -564,12 +551,11 @@ __global__ void k_reset_batch(Args a) {
     b->evals = 0u;
 }
 
-// Clears the tickets and marks every system idle (after ff_create).
+// Marks every system idle (after ff_create).
 __global__ void k_reset_ctl(Args a) {
     if (threadIdx.x != 0) return;
     Ctl* c = ctl_at(a, blockIdx.x);
     c->batch = nullptr;
-    for (int k = 0; k < kTicketSlots; ++k) c->ticket_fin[k] = c->ticket_acc[k] = 0u;
     c->action = ACT_NONE;
     c->accept = 0;
     c->done = 1;
@@ -579,14 +565,17 @@ __global__ void k_reset_ctl(Args a) {
 
 hipError_t launch_finalize(const Args& a, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(a.L.max_fin_blocks, 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
+    hipLaunchKernelGGL(k_fin_reduce, dim3(a.L.n_sys), dim3(kFinBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s) {
     if (which == 0)
         hipLaunchKernelGGL(k_prepare, dim3(a.L.max_vec_blocks, 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
-    else
+    else {
         hipLaunchKernelGGL(k_accept, dim3(a.L.accept_bx, kMaxM + 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
+        hipLaunchKernelGGL(k_accept_reduce, dim3(a.L.n_sys), dim3(kFinBlock), 0, s, a);
+    }
     return hipGetLastError();
 }
 
