@@ -48,8 +48,12 @@ typedef enum {
 
 /* Methods of section 5.1: steepest descent with a line search (section 4,
  * eq. 4), FGM (Algorithm 1), CG with the Polak-Ribiere-Polyak beta
- * (Algorithm 2), L-BFGS (Algorithms 3 and 4). */
-typedef enum { FF_GD = 0, FF_FGM = 1, FF_CG = 2, FF_LBFGS = 3 } ff_method;
+ * (Algorithm 2), L-BFGS (Algorithms 3 and 4); and of section 4: the heavy-ball
+ * method (eq. HB, constant steps hb_alpha, hb_beta, no line search) and the
+ * optimized gradient method (eq. optim, with the line search the text puts
+ * in place of 1/L, restarting at the current point when its direction is not
+ * a descent direction or the line search fails). */
+typedef enum { FF_GD = 0, FF_FGM = 1, FF_CG = 2, FF_LBFGS = 3, FF_HB = 4, FF_OGM = 5 } ff_method;
 
 /* Arithmetic of the pair sum.  FF_FP64: FP64 throughout.  FF_FP32_ACC64:
  * pair terms in FP32 on double-single coordinate differences, accumulated
@@ -63,7 +67,9 @@ typedef enum {
     FF_MAX_ITER = 1,          /* max_iter iterations done */
     FF_LS_FAILED = 2,         /* no relaxing step even after the restart
                                  (the "dead end" of section 5.1) */
-    FF_NONFINITE_START = 3    /* E or grad E not finite at the start point */
+    FF_NONFINITE_START = 3,   /* E or grad E not finite at the start point */
+    FF_DIVERGED = 4           /* heavy ball: a step reached a non-finite E or
+                                 grad E (the last finite iterate is returned) */
 } ff_term;
 
 /* beta of the CG variants named in section 5.1 (y = g_{k+1} - g_k, d = the
@@ -126,6 +132,8 @@ typedef struct {
                              iterate's energy exceeds the previous one
                              (function-value adaptive restart); 0: Algorithm 1
                              as printed [0] */
+    double hb_alpha;      /* heavy ball: gradient step, > 0 (required) [0] */
+    double hb_beta;       /* heavy ball: momentum, in [0, 1) [0] */
 } ff_min_params;
 
 /* Outcome of ff_minimize (host struct). */
@@ -211,8 +219,8 @@ ff_status ff_energy_grad(ff_ctx *ctx, const double *xyz, double *energy, double 
                          int32_t precision, void *stream);
 
 /* Local minimization from xyz_inout (device, concatenated [n][3]); on return
- * it holds the result points: the last iterate for GD, CG and L-BFGS, the best
- * iterate for FGM (Algorithm 1).  result: host array of n_sys entries.
+ * it holds the result points: the last iterate for GD, CG, L-BFGS, heavy ball
+ * and OGM, the best iterate for FGM (Algorithm 1).  result: host array of n_sys entries.
  * Blocks until every system has stopped. */
 ff_status ff_minimize(ff_ctx *ctx, double *xyz_inout, const ff_min_params *params,
                       ff_min_result *result, void *stream);

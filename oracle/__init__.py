@@ -10,13 +10,13 @@ shares no code with the HIP path.
 * ``minimize`` (Python): the line searches LS_H and LS_PAR (section 5.2,
   Algorithms 5 and 6) and the methods GD (steepest descent with a line search,
   eq. 4), FGM (Algorithm 1), CG (Algorithm 2, Polak-Ribiere-Polyak beta of
-  section 4) and L-BFGS (Algorithms 3 and 4), in the paper's order and
-  notation.
+  section 4) and L-BFGS (Algorithms 3 and 4), heavy ball (eq. HB) and the
+  optimized gradient method (eq. optim), in the paper's order and notation.
 """
 from .energy import System, energy_grad, energy_terms, atom_gradients, num_threads, build  # noqa: F401
 from .minimize import (  # noqa: F401
-    MinParams, MinResult, minimize, ls_par, ls_h, lbfgs_direction, fgm_coefficients,
-    GD, FGM, CG, LBFGS, LS_PAR, LS_H, cg_beta,
+    MinParams, MinResult, minimize, ls_par, ls_h, lbfgs_direction, fgm_coefficients, ogm_t_next,
+    GD, FGM, CG, LBFGS, HB, OGM, LS_PAR, LS_H, cg_beta,
     CG_PRP, CG_FR, CG_HS, CG_PRP_PLUS, CG_CD, CG_LS, CG_DY,
-    CONVERGED, MAX_ITER, LS_FAILED, NONFINITE_START,
+    CONVERGED, MAX_ITER, LS_FAILED, NONFINITE_START, DIVERGED,
 )

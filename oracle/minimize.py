@@ -41,6 +41,19 @@ the rule the GPU library implements as well):
 * optional FGM variant (off by default): the adaptive restart of O'Donoghue
   and Candes 2015 sets theta back to 1 whenever an iterate has a higher
   energy than the one before it;
+* heavy ball (eq. HB) runs as printed: constant alpha and beta, x^{-1} = x^0,
+  no line search and no normalization; a non-finite E or gradient at a new
+  iterate stops the run with DIVERGED (the last finite iterate is returned);
+* the optimized gradient method (eq. optim) replaces 1/L by a line search
+  from y^{k+1} along -d^{k+1}/|d^{k+1}|, as the text following the method
+  suggests, with the methods' default line search (LS_PAR, then LS_H);
+  t_0 = 1 and the anchor x^0 is the start point; E and its gradient are
+  evaluated at y^{k+1} unless y^{k+1} is the current point (the anchor is
+  the current point right after a (re)start, where the direction is -g);
+  when the direction is not a descent direction at y^{k+1} or the line search
+  fails, the method restarts at the current point (x^0 := x^k, t := 1, the
+  gradient sum := the current gradient); a failure right after a restart
+  stops the run with LS_FAILED; the last iterate is returned;
 * stop when |grad|_inf < tol at the current point (FGM: at its best point),
   or after max_iter iterations.
 """
@@ -52,11 +65,11 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-GD, FGM, CG, LBFGS = 0, 1, 2, 3
+GD, FGM, CG, LBFGS, HB, OGM = 0, 1, 2, 3, 4, 5
 LS_PAR, LS_H = 0, 1
 # CG beta variants named in section 5.1 (formulas as collected by Andrei 2008)
 CG_PRP, CG_FR, CG_HS, CG_PRP_PLUS, CG_CD, CG_LS, CG_DY = 0, 1, 2, 3, 4, 5, 6
-CONVERGED, MAX_ITER, LS_FAILED, NONFINITE_START = 0, 1, 2, 3
+CONVERGED, MAX_ITER, LS_FAILED, NONFINITE_START, DIVERGED = 0, 1, 2, 3, 4
 EPS_MACH = float(np.finfo(np.float64).eps)
 
 
@@ -76,6 +89,8 @@ class MinParams:
     cg_beta: int = CG_PRP
     ls_par_g0: bool = True      # Algorithm 6's G0: use f and the slope at the base point
     fgm_restart: bool = False   # restart FGM's momentum when f(x^{k+1}) > f(x^k)
+    hb_alpha: float = 0.0       # heavy ball: step on the gradient (> 0)
+    hb_beta: float = 0.0        # heavy ball: momentum in [0, 1)
 
     def primary_ls(self) -> int:
         if self.linesearch in (LS_PAR, LS_H):
@@ -362,6 +377,84 @@ def _fgm(fg, x, f, g, p: MinParams, res: MinResult):
     res.x, res.f, res.g, res.iters = best[0], best[1], best[2], k
 
 
+def _heavy_ball(fg, x, f, g, p: MinParams, res: MinResult):
+    """Eq. HB: x^{k+1} = x^k - alpha grad f(x^k) + beta (x^k - x^{k-1})."""
+    x_prev = x
+    k = 0
+    while True:
+        if _ginf(g) < p.tol:
+            res.term = CONVERGED
+            break
+        if k == p.max_iter:
+            res.term = MAX_ITER
+            break
+        x_new = x - p.hb_alpha * g + p.hb_beta * (x - x_prev)
+        f_new, g_new = fg(x_new)
+        if not _finite_point(f_new, g_new):
+            res.term = DIVERGED
+            break
+        x_prev, x, f, g = x, x_new, f_new, g_new
+        k += 1
+        res.trace.append((f, p.hb_alpha, res.evals))
+    res.x, res.f, res.g, res.iters = x, f, g, k
+
+
+def ogm_t_next(t: float) -> float:
+    """t_{k+1} of eq. optim from t_k."""
+    return 0.5 * (1.0 + math.sqrt(4.0 * t * t + 1.0))
+
+
+def _ogm(fg, x, f, g, p: MinParams, res: MinResult):
+    """Eq. optim with the line search in place of 1/L:
+    y^{k+1} = (1 - 1/t_{k+1}) x^k + x^0 / t_{k+1},
+    d^{k+1} = (1 - 1/t_{k+1}) g(x^k) + (2/t_{k+1}) sum_{j<=k} t_j g(x^j),
+    x^{k+1} = y^{k+1} + h r with r = -d^{k+1}/|d^{k+1}|."""
+    x0 = x                      # anchor
+    t = 1.0                     # t_0
+    S = g.copy()                # sum_j t_j g(x^j) = t_0 g(x^0)
+    h_prev = p.h_init
+    k = 0
+    while True:
+        if _ginf(g) < p.tol:
+            res.term = CONVERGED
+            break
+        if k == p.max_iter:
+            res.term = MAX_ITER
+            break
+        t_next = ogm_t_next(t)
+        th = 1.0 / t_next
+        d = (1.0 - th) * g + (2.0 * th) * S
+        at_anchor = x0 is x
+        if at_anchor:
+            y, fy, gy = x, f, g
+        else:
+            y = (1.0 - th) * x + th * x0
+            fy, gy = fg(y)
+        dn = float(np.linalg.norm(d))
+        ok = _finite_point(fy, gy) and dn > 0.0 and math.isfinite(dn)
+        if ok:
+            r = -d / dn
+            s0 = float(np.dot(gy, r))
+            ok = s0 < 0.0
+        if ok:
+            ok, h, f_new, g_new = _search(fg, y, r, h_prev, fy, s0, p)
+        if not ok:
+            if not at_anchor:           # restart at the current point
+                x0, t, S = x, 1.0, g.copy()
+                h_prev = p.h_init
+                continue
+            res.term = LS_FAILED
+            break
+        x = y + h * r
+        f, g = f_new, g_new
+        t = t_next
+        S = S + t * g
+        h_prev = abs(h)
+        k += 1
+        res.trace.append((f, h, res.evals))
+    res.x, res.f, res.g, res.iters = x, f, g, k
+
+
 def minimize(fg, x0, p: MinParams | None = None) -> MinResult:
     """Local minimization from x0 (section 2: the local minimum reachable from
     a good start)."""
@@ -382,6 +475,12 @@ def minimize(fg, x0, p: MinParams | None = None) -> MinResult:
         _fgm(counted, x, f, g, p, res)
     elif p.method in (GD, CG, LBFGS):
         _gd_cg_lbfgs(counted, x, f, g, p, res)
+    elif p.method == HB:
+        if not (p.hb_alpha > 0.0 and 0.0 <= p.hb_beta < 1.0):
+            raise ValueError("heavy ball needs hb_alpha > 0 and 0 <= hb_beta < 1")
+        _heavy_ball(counted, x, f, g, p, res)
+    elif p.method == OGM:
+        _ogm(counted, x, f, g, p, res)
     else:
         raise ValueError(f"unknown method {p.method}")
     return res

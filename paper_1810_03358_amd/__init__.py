@@ -15,8 +15,8 @@ import torch
 
 from . import _native as N
 from ._native import (  # noqa: F401
-    FF_GD, FF_FGM, FF_CG, FF_LBFGS, FF_FP64, FF_FP32_ACC64,
-    FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START,
+    FF_GD, FF_FGM, FF_CG, FF_LBFGS, FF_HB, FF_OGM, FF_FP64, FF_FP32_ACC64,
+    FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START, FF_DIVERGED,
     FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H, FF_MIN_RESUME, FF_MIN_NO_CERTIFY,
     FF_OK, FF_ERR_ARG, FF_ERR_HIP, FF_ERR_WORKSPACE, FF_ERR_UNSUPPORTED,
     FF_CG_PRP, FF_CG_FR, FF_CG_HS, FF_CG_PRP_PLUS, FF_CG_CD, FF_CG_LS, FF_CG_DY,
@@ -24,10 +24,10 @@ from ._native import (  # noqa: F401
 CG_BETAS = {"prp": FF_CG_PRP, "fr": FF_CG_FR, "hs": FF_CG_HS, "prp+": FF_CG_PRP_PLUS, "cd": FF_CG_CD,
             "ls": FF_CG_LS, "dy": FF_CG_DY}
 
-METHODS = {"gd": FF_GD, "fgm": FF_FGM, "cg": FF_CG, "lbfgs": FF_LBFGS}
+METHODS = {"gd": FF_GD, "fgm": FF_FGM, "cg": FF_CG, "lbfgs": FF_LBFGS, "hb": FF_HB, "ogm": FF_OGM}
 PRECISIONS = {"fp64": FF_FP64, "fp32": FF_FP32_ACC64}
 TERMS = {FF_CONVERGED: "converged", FF_MAX_ITER: "max_iter", FF_LS_FAILED: "ls_failed",
-         FF_NONFINITE_START: "nonfinite_start"}
+         FF_NONFINITE_START: "nonfinite_start", FF_DIVERGED: "diverged"}
 
 
 class FFError(RuntimeError):
@@ -183,7 +183,8 @@ class Context:
                  max_iter: int = 2000, precision: str | int = "fp64", linesearch: int = FF_LS_DEFAULT,
                  ls_K: int = 2, h_init: float = 0.1, k_plus: float = 2.0, k_minus: float = 0.5,
                  eps_h: float = 1e-10, cg_restart: int = 0, cg_beta: str | int = "prp", ls_par_g0: bool = True,
-                 fgm_restart: bool = False, resume: bool = False, certify: bool = True, stream=None) -> dict:
+                 fgm_restart: bool = False, hb_alpha: float = 0.0, hb_beta: float = 0.0, resume: bool = False,
+                 certify: bool = True, stream=None) -> dict:
         """Minimize in place (x is overwritten with the result point(s)); blocks.
         Returns a result dict (a list of them for a batch)."""
         x = self._coords(x)
@@ -198,6 +199,7 @@ class Context:
         p.cg_beta = CG_BETAS.get(cg_beta, cg_beta)
         p.ls_par_g0 = 1 if ls_par_g0 else 0
         p.fgm_restart = 1 if fgm_restart else 0
+        p.hb_alpha, p.hb_beta = hb_alpha, hb_beta
         p.flags = (FF_MIN_RESUME if resume else 0) | (0 if certify else FF_MIN_NO_CERTIFY)
         res = (N.FFMinResult * self.n_sys)()
         _check(N.load().ff_minimize(self._ctx, C.c_void_p(x.data_ptr()), C.byref(p), res,

@@ -8,9 +8,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libff_mi355x.so")
 
 FF_OK, FF_ERR_ARG, FF_ERR_HIP, FF_ERR_WORKSPACE, FF_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
-FF_GD, FF_FGM, FF_CG, FF_LBFGS = 0, 1, 2, 3
+FF_GD, FF_FGM, FF_CG, FF_LBFGS, FF_HB, FF_OGM = 0, 1, 2, 3, 4, 5
 FF_FP64, FF_FP32_ACC64 = 0, 1
-FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START = 0, 1, 2, 3
+FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START, FF_DIVERGED = 0, 1, 2, 3, 4
 FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H = -1, 0, 1
 FF_MIN_RESUME, FF_MIN_NO_CERTIFY = 1, 2
 FF_CG_PRP, FF_CG_FR, FF_CG_HS, FF_CG_PRP_PLUS, FF_CG_CD, FF_CG_LS, FF_CG_DY = 0, 1, 2, 3, 4, 5, 6
@@ -35,7 +35,7 @@ class FFMinParams(C.Structure):
         ("precision", C.c_int32), ("linesearch", C.c_int32), ("ls_K", C.c_int32),
         ("h_init", C.c_double), ("k_plus", C.c_double), ("k_minus", C.c_double), ("eps_h", C.c_double),
         ("cg_restart", C.c_int32), ("flags", C.c_int32), ("cg_beta", C.c_int32), ("ls_par_g0", C.c_int32),
-        ("fgm_restart", C.c_int32),
+        ("fgm_restart", C.c_int32), ("hb_alpha", C.c_double), ("hb_beta", C.c_double),
     ]
 
 

@@ -296,6 +296,8 @@ void ff_default_params(ff_min_params* p) {
     p->cg_beta = FF_CG_PRP;
     p->ls_par_g0 = 1;
     p->fgm_restart = 0;
+    p->hb_alpha = 0.0;
+    p->hb_beta = 0.0;
 }
 
 const char* ff_last_error(void) { return g_err.c_str(); }
@@ -625,7 +627,10 @@ static ff_status build_graph(ff_ctx* c) {
 ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_result* res, void* stream) {
     g_err.clear();
     if (!c || !xyz || !p || !res) return fail(FF_ERR_ARG, "null argument");
-    if (p->method < FF_GD || p->method > FF_LBFGS) return fail(FF_ERR_ARG, "bad method %d", p->method);
+    if (p->method < FF_GD || p->method > FF_OGM) return fail(FF_ERR_ARG, "bad method %d", p->method);
+    if (p->method == FF_HB && !(p->hb_alpha > 0.0 && std::isfinite(p->hb_alpha) && p->hb_beta >= 0.0 &&
+                                p->hb_beta < 1.0))
+        return fail(FF_ERR_ARG, "heavy ball needs hb_alpha > 0 and 0 <= hb_beta < 1");
     if (p->method == FF_LBFGS && (p->m < 1 || p->m > c->L.m_max))
         return fail(FF_ERR_ARG, "m = %d outside [1, m_max = %d]", p->m, c->L.m_max);
     if (!(p->tol > 0.0)) return fail(FF_ERR_ARG, "tol must be > 0");
@@ -666,6 +671,8 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     d.k_plus = p->k_plus;
     d.k_minus = p->k_minus;
     d.eps_h = p->eps_h;
+    d.hb_alpha = p->hb_alpha;
+    d.hb_beta = p->hb_beta;
     double* x0 = at<double>(c->ws, L.off_vec) + (size_t)V_X0 * L.vstride;
     if (!resume)
         for (int k = 0; k < L.n_sys; ++k)

@@ -42,8 +42,8 @@
 
 namespace ff {
 
-enum { M_GD = 0, M_FGM = 1, M_CG = 2, M_LBFGS = 3 };
-enum { T_CONVERGED = 0, T_MAX_ITER = 1, T_LS_FAILED = 2, T_NONFINITE = 3 };
+enum { M_GD = 0, M_FGM = 1, M_CG = 2, M_LBFGS = 3, M_HB = 4, M_OGM = 5 };
+enum { T_CONVERGED = 0, T_MAX_ITER = 1, T_LS_FAILED = 2, T_NONFINITE = 3, T_DIVERGED = 4 };
 enum { P_FP64 = 0, P_FP32 = 1 };
 
 constexpr double kEpsMach = 2.220446049250313e-16;
@@ -73,6 +73,7 @@ __device__ inline void request_eval(Ctl* c, int mode, int target, int want_slope
     c->target = target;
     c->prec = c->prec_now;
     c->want_slope = want_slope;
+    c->slope_slot = mode == PM_OGM_Y ? target : c->base;
     c->accept = 0;
 }
 
@@ -100,6 +101,15 @@ __device__ inline void finish(Ctl* c, int term) {
 
 __device__ inline void lbfgs_clear(Ctl* c);
 
+// OGM restart at the current point: anchor x^0 := x^k, t := 1, and the
+// weighted gradient sum := the current gradient.
+__device__ inline void ogm_restart(Ctl* c) {
+    c->prev_x = c->cur;
+    c->ogm_t = 1.0;
+    c->ogm_s_anchor = 1;
+    c->h_prev = c->p.h_init;
+}
+
 // Re-evaluate `slot` in FP64 (precision escalation of the mixed mode).  The
 // stored L-BFGS pairs and the CG direction were built from FP32 gradients
 // and their products with g would no longer match the FP64 gradient, so the
@@ -110,6 +120,7 @@ __device__ inline void escalate(Ctl* c, int slot) {
     c->phase = PH_REEVAL64;
     c->steepest = 1;
     lbfgs_clear(c);
+    if (c->p.method == M_OGM) ogm_restart(c);
     request_eval(c, PM_USE, slot, 0);
 }
 
@@ -334,6 +345,45 @@ __device__ inline void begin_iteration(Ctl* c) {
             set_steepest(c);
         }
         break;
+    case M_HB: {
+        // eq. HB: x^{k+1} = x^k - alpha g^k + beta (x^k - x^{k-1}), no line search
+        const int t = alloc_slot(c);
+        c->base = c->cur;
+        c->prev = c->prev_x;
+        c->h = p.hb_alpha;
+        c->beta = p.hb_beta;
+        c->phase = PH_HB;
+        request_eval(c, PM_HB, t, 0);
+        return;
+    }
+    case M_OGM: {
+        // eq. optim: d = (1 - 1/t+) g^k + (2/t+) S, S = sum_j t_j g^j; the search
+        // runs from y = (1 - 1/t+) x^k + x^0 / t+ along r = -d/|d|
+        const double t_next = 0.5 * (1.0 + sqrt(4.0 * c->ogm_t * c->ogm_t + 1.0));
+        const double th = 1.0 / t_next;
+        const double a = 1.0 - th, b = 2.0 * th;
+        const double gg = c->g2[c->cur];
+        const double gS = c->ogm_s_anchor ? gg : c->ogm_gS;
+        const double SS = c->ogm_s_anchor ? gg : c->ogm_SS;
+        c->ogm_t_next = t_next;
+        c->n_terms = 2;
+        c->term_vec[0] = V_G0 + c->cur;
+        c->term_coef[0] = -a;
+        c->term_vec[1] = c->ogm_s_anchor ? V_G0 + c->prev_x : V_R;
+        c->term_coef[1] = -b;
+        c->dir_scale = sqrt(a * a * gg + 2.0 * a * b * gS + b * b * SS);
+        c->steepest = c->prev_x == c->cur;
+        if (c->prev_x != c->cur) {
+            c->w = alloc_slot(c);
+            c->base = c->cur;
+            c->prev = c->prev_x;
+            c->beta = th;
+            c->phase = PH_OGM_Y;
+            request_eval(c, PM_OGM_Y, c->w, 1);     // E, grad E and <grad E(y), r> at y
+            return;
+        }
+        break;    // the anchor is the current point: y = x^k, r = -g/|g|
+    }
     case M_FGM: {
         const double tp = c->theta_prev;
         const double theta = 0.5 * tp * (sqrt(tp * tp + 4.0) - tp);
@@ -379,8 +429,10 @@ __device__ void ls_success(Ctl* c, int slot, double h) {
     c->accept = 1;
     c->acc_new = slot;
     c->acc_old = c->ls_base;
-    // L-BFGS: the new pair's own products, then one row per stored pair
-    c->acc_rows = c->p.method == M_LBFGS ? c->hist_n + 1 : (c->p.method == M_CG ? 1 : 0);
+    // L-BFGS: the new pair's own products, then one row per stored pair;
+    // CG: its beta products; OGM: the update of its gradient sum
+    c->acc_rows = c->p.method == M_LBFGS ? c->hist_n + 1
+                : (c->p.method == M_CG || c->p.method == M_OGM ? 1 : 0);
     c->action = ACT_NONE;
 }
 
@@ -395,6 +447,11 @@ __device__ void ls_failed(Ctl* c) {
         c->steepest = 1;
         lbfgs_clear(c);
         c->h_prev = p.h_init;
+        begin_iteration(c);
+        return;
+    }
+    if (p.method == M_OGM && c->prev_x != c->cur) {
+        ogm_restart(c);
         begin_iteration(c);
         return;
     }
@@ -502,6 +559,18 @@ __device__ inline bool accept_update(Ctl* c, const double* dots) {
         c->cur = nw;
         return c->hist_n > 0;
     }
+    case M_HB:
+        c->prev_x = c->cur;          // x^{k-1}
+        c->cur = nw;
+        break;
+    case M_OGM:
+        // dots: [0] <g_new, S_new>, [1] <S_new, S_new> with S_new = S + t+ g_new
+        c->cur = nw;
+        c->ogm_t = c->ogm_t_next;
+        c->ogm_gS = dots[0];
+        c->ogm_SS = dots[1];
+        c->ogm_s_anchor = 0;
+        break;
     case M_FGM: {
         const double f_old = c->e[c->cur];
         c->prev_x = c->cur;
@@ -557,6 +626,28 @@ __device__ inline void after_eval(Ctl* c) {
     case PH_CERTIFY:
         finish_done(c, t);
         return;
+    case PH_HB:
+        if (!isfinite(c->e[t]) || !isfinite(c->g2[t])) { finish(c, T_DIVERGED); return; }
+        c->accept_h = c->p.hb_alpha;
+        c->accept = 1;
+        c->acc_new = t;
+        c->acc_old = c->cur;
+        c->acc_rows = 0;
+        c->action = ACT_NONE;
+        return;
+    case PH_OGM_Y: {
+        const bool ok = isfinite(c->e[t]) && isfinite(c->g2[t]) && isfinite(c->slope) && c->slope < 0.0 &&
+                        isfinite(c->dir_scale) && c->dir_scale > 0.0;
+        if (!ok) {                                  // not a descent direction at y: restart
+            ogm_restart(c);
+            begin_iteration(c);
+            return;
+        }
+        const int primary = c->p.linesearch == 1 ? LSK_H : LSK_PAR;
+        c->ls_fallback_done = primary == LSK_H;
+        ls_start(c, t, c->h_prev, primary, false);  // direction and slope from the y evaluation
+        return;
+    }
     default:
         c->action = ACT_NONE;
         return;

@@ -55,10 +55,12 @@ enum PointMode : int32_t {
     PM_USE = 0,        // evaluate x[target] as it is
     PM_TRIAL = 1,      // x[target] = x[base] + h * d
     PM_DIR_TRIAL = 2,  // d = sum_k coef_k v_k (optionally also r), then as PM_TRIAL
-    PM_MOMENTUM = 3    // x[target] = x[base] + beta * (x[base] - x[prev])
+    PM_MOMENTUM = 3,   // x[target] = x[base] + beta * (x[base] - x[prev])
+    PM_HB = 4,         // x[target] = x[base] - h g[base] + beta (x[base] - x[prev])
+    PM_OGM_Y = 5       // d as in PM_DIR_TRIAL, x[target] = (1 - beta) x[base] + beta x[prev]
 };
 enum Phase : int32_t {
-    PH_IDLE = 0, PH_START, PH_LS, PH_MOMENTUM, PH_REEVAL64, PH_CERTIFY, PH_DONE
+    PH_IDLE = 0, PH_START, PH_LS, PH_MOMENTUM, PH_REEVAL64, PH_CERTIFY, PH_DONE, PH_HB, PH_OGM_Y
 };
 enum LsKind : int32_t { LSK_PAR = 0, LSK_H = 1 };
 enum LsHStage : int32_t { LSH_F0 = 0, LSH_F1 = 1, LSH_SHRINK = 2 };
@@ -71,7 +73,7 @@ struct BatchState {
 
 struct MinParamsDev {
     int32_t method, m, max_iter, precision, linesearch, ls_K, cg_restart, certify, cg_beta, ls_g0, fgm_restart;
-    double tol, h_init, k_plus, k_minus, eps_h;
+    double tol, h_init, k_plus, k_minus, eps_h, hb_alpha, hb_beta;
 };
 
 struct Ctl {
@@ -82,7 +84,8 @@ struct Ctl {
     int32_t target;          // slot evaluated
     int32_t base;            // trial base slot
     int32_t prev;            // momentum: previous point slot
-    int32_t want_slope;      // finalize also computes <g[base], d>
+    int32_t want_slope;      // finalize also computes <g[slope_slot], d>
+    int32_t slope_slot;      // base point of that product (the evaluated point for PM_OGM_Y)
     int32_t write_r;         // PM_DIR_TRIAL: also store the unnormalized r
     double h;                // trial step
     double beta;             // momentum coefficient
@@ -117,6 +120,11 @@ struct Ctl {
     double theta_prev, fgm_theta, fgm_beta;  // FGM
     double accept_h;                         // step of the last accepted trial
     double cg_beta, r_norm2, r_dot_g_old, g_dot_g_old;   // CG
+    // OGM: t_k, t_{k+1}, and <g, S>, <S, S> of the weighted gradient sum S
+    // (vector V_R; before the first accept after a (re)start S is the anchor's
+    // gradient itself: ogm_s_anchor = 1).  The anchor x^0 is slot prev_x.
+    double ogm_t, ogm_t_next, ogm_gS, ogm_SS;
+    int32_t ogm_s_anchor;
     // L-BFGS history: a ring of hist_m slots; stored pair i (0 = oldest,
     // i < hist_n) sits in slot (hist_head + i) mod hist_m.  Everything below
     // is indexed by slot, so storing a pair never moves the others.

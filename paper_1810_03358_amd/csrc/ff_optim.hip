@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     v[1] = gx * gx + gy * gy + gz * gz;
     v[2] = 0.0;
     if (want_slope && real) {
-        const double* gb = vec(a, V_G0 + c->base, si);
+        const double* gb = vec(a, V_G0 + c->slope_slot, si);
         const double* d = vec(a, V_D, si);
         const size_t o = 3 * (size_t)atom;
         v[2] = gb[o] * d[o] + gb[o + 1] * d[o + 1] + gb[o + 2] * d[o + 2];
@@ -350,20 +350,27 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
     const Ctl* c = ctl_at(a, sys);
     if (c->action != ACT_EVAL || c->point_mode == PM_USE) return;
     if (c->target < 0 || c->target >= kNumSlots || c->base < 0 || c->base >= kNumSlots) return;
-    if (c->point_mode == PM_MOMENTUM && (c->prev < 0 || c->prev >= kNumSlots)) return;
+    const int pm = c->point_mode;
+    if ((pm == PM_MOMENTUM || pm == PM_HB || pm == PM_OGM_Y) && (c->prev < 0 || c->prev >= kNumSlots)) return;
     const int n3 = 3 * si.n;
     const int i = blockIdx.x * kFinBlock + threadIdx.x;
     if (i >= n3) return;
     double* xt = vec(a, V_X0 + c->target, si);
     const double* xb = vec(a, V_X0 + c->base, si);
-    if (c->point_mode == PM_MOMENTUM) {
+    if (pm == PM_MOMENTUM) {
         const double* xp = vec(a, V_X0 + c->prev, si);
         xt[i] = __dadd_rn(xb[i], __dmul_rn(c->beta, __dsub_rn(xb[i], xp[i])));
         return;
     }
+    if (pm == PM_HB) {
+        const double* xp = vec(a, V_X0 + c->prev, si);
+        const double* gb = vec(a, V_G0 + c->base, si);
+        xt[i] = __dadd_rn(__dsub_rn(xb[i], __dmul_rn(c->h, gb[i])), __dmul_rn(c->beta, __dsub_rn(xb[i], xp[i])));
+        return;
+    }
     double* d = vec(a, V_D, si);
     double di;
-    if (c->point_mode == PM_DIR_TRIAL) {
+    if (pm == PM_DIR_TRIAL || pm == PM_OGM_Y) {
         double r = __dmul_rn(c->term_coef[0], vec(a, c->term_vec[0], si)[i]);
         for (int k = 1; k < c->n_terms; ++k) r = __dadd_rn(r, __dmul_rn(c->term_coef[k], vec(a, c->term_vec[k], si)[i]));
         if (c->write_r) vec(a, V_R, si)[i] = r;
@@ -371,6 +378,11 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
         d[i] = di;
     } else {
         di = d[i];
+    }
+    if (pm == PM_OGM_Y) {
+        const double* xa = vec(a, V_X0 + c->prev, si);
+        xt[i] = __dadd_rn(__dmul_rn(1.0 - c->beta, xb[i]), __dmul_rn(c->beta, xa[i]));
+        return;
     }
     xt[i] = __dadd_rn(xb[i], __dmul_rn(c->h, di));
 }
@@ -409,7 +421,18 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
         const double* gn = vec(a, V_G0 + c->acc_new, si);
         const double* go = vec(a, V_G0 + c->acc_old, si);
         const int stride = nbx * kFinBlock;
-        if (method == M_CG) {
+        if (method == M_OGM) {
+            // S += t_{k+1} g_new (S is the anchor's gradient after a restart)
+            const double* src = c->ogm_s_anchor ? vec(a, V_G0 + c->prev_x, si) : vec(a, V_R, si);
+            double* S = vec(a, V_R, si);
+            const double t = c->ogm_t_next;
+            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+                const double sn = __dadd_rn(src[i], __dmul_rn(t, gn[i]));
+                S[i] = sn;
+                v[0] += gn[i] * sn;
+                v[1] += sn * sn;
+            }
+        } else if (method == M_CG) {
             const double* r = vec(a, V_R, si);
             for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 v[0] += gn[i] * go[i];
@@ -460,7 +483,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept_reduce(Args a) {
     const int nbx = a.L.accept_bx;
     const double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     __shared__ double dots[kMaxDots];
-    const int nd = method == M_LBFGS ? 6 * rows : (method == M_CG ? 3 : 0);
+    const int nd = method == M_LBFGS || method == M_OGM ? 6 * rows : (method == M_CG ? 3 : 0);
     for (int k = threadIdx.x; k < nd; k += kFinBlock) {
         const int r = k / 6, q = k - 6 * r;
         double acc = 0.0;
@@ -521,7 +544,9 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
     c->evals64 = 0;
     c->iters_limit = p.max_iter;
     c->cur = 0;
-    c->prev_x = p.method == M_FGM ? 0 : -1;
+    c->prev_x = (p.method == M_FGM || p.method == M_HB || p.method == M_OGM) ? 0 : -1;
+    c->ogm_t = 1.0;
+    c->ogm_s_anchor = 1;
     c->best = -1;
     c->w = -1;
     c->ls_base = -1;

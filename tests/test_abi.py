@@ -37,6 +37,7 @@ def test_default_params():
         ff.FF_LBFGS, 10, 1e-3, 2000, ff.FF_FP64, ff.FF_LS_DEFAULT, 2)
     assert (p.h_init, p.k_plus, p.k_minus, p.eps_h, p.cg_restart, p.flags) == (0.1, 2.0, 0.5, 1e-10, 0, 0)
     assert (p.cg_beta, p.ls_par_g0, p.fgm_restart) == (ff.FF_CG_PRP, 1, 0)
+    assert (p.hb_alpha, p.hb_beta) == (0.0, 0.0)
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 512, 513, 10_000, 50_000])

@@ -10,6 +10,10 @@ moves its own energies by 1e-11 (GD), 1e-9 (CG), 4e-12 (L-BFGS) and 2e-3
 5e-6 at iteration 40 for FGM with restarts, with identical decisions.  So
 iterations 20..50 are gated at 1e-6 relative for GD, CG and L-BFGS, and the
 FGM variants' energies are compared up to iteration 30.
+Heavy ball (no decisions) amplifies a one-ulp perturbation to 1e-14 over 100
+iterations and the optimized gradient method to 1.4e-13 over 50 on chain512
+(every iteration gated at 1e-9), to 9e-10 on a 300-atom torsion chain (1e-9
+for 10 iterations, then 1e-6).
 FP32 mode is checked on its final state: the certified energy and gradient
 norm reported for the returned point must be what the oracle computes there.
 """
@@ -26,7 +30,8 @@ from tests.systems import make_system, torsion_chain
 
 pytestmark = pytest.mark.gpu
 
-OMETHOD = {"gd": oracle.GD, "fgm": oracle.FGM, "cg": oracle.CG, "lbfgs": oracle.LBFGS}
+OMETHOD = {"gd": oracle.GD, "fgm": oracle.FGM, "cg": oracle.CG, "lbfgs": oracle.LBFGS, "hb": oracle.HB,
+           "ogm": oracle.OGM}
 
 
 def oracle_run(s, method, **kw):
@@ -179,3 +184,35 @@ def test_fp32_converges_with_fp64_end_game():
     assert r["evals_fp64"] >= 1
     e_ref, g_ref = oracle.energy_grad(s, x)
     assert np.abs(g_ref).max() < 1e-3
+
+
+def test_fp64_heavy_ball_matches_the_oracle():
+    s = torsion_chain(300, 7)
+    kw = dict(max_iter=100, hb_alpha=1e-3, hb_beta=0.8)
+    ref = oracle_run(s, "hb", **kw)
+    r, _, tr, _ = gpu_run(s, "hb", **kw)
+    assert r["term"] == ref.term and r["iters"] == ref.iters == 100 and r["evals"] == ref.evals == 101
+    compare_traces(tr, ref, 100, tight=100)
+    assert np.all(tr[:100, 1] == 1e-3)
+
+
+def test_heavy_ball_divergence_stops_at_the_last_finite_point():
+    s = torsion_chain(120, 9)
+    kw = dict(max_iter=10, hb_alpha=1e300, hb_beta=0.0)
+    ref = oracle_run(s, "hb", **kw)
+    r, x, _, _ = gpu_run(s, "hb", **kw)
+    assert ref.term == oracle.DIVERGED and r["term"] == ff.FF_DIVERGED
+    assert r["iters"] == ref.iters == 0 and r["evals"] == ref.evals == 2
+    np.testing.assert_array_equal(x, s["x"])
+    assert r["energy"] == pytest.approx(ref.f, rel=1e-12)
+
+
+@pytest.mark.parametrize("system", ["chain512", "torsion300"])
+def test_fp64_ogm_iterates_match_the_oracle(system):
+    s = config_system("chain512") if system == "chain512" else torsion_chain(300, 7)
+    ref = oracle_run(s, "ogm", max_iter=50)
+    r, _, tr, _ = gpu_run(s, "ogm", max_iter=50)
+    assert r["term"] == ref.term and r["iters"] == ref.iters and r["evals"] == ref.evals
+    # a one-ulp perturbation grows to 1.4e-13 (chain512) and 9e-10 (torsion300)
+    # by iteration 50 in the oracle itself
+    compare_traces(tr, ref, 50, tight=50 if system == "chain512" else 10)

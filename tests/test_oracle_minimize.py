@@ -305,3 +305,120 @@ def test_ls_par_without_g0_is_exact_on_a_parabola():
     ok, h, f, _, hmin = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, c, 0.0, K=3, g0=False)
     assert probes[:2] == [-0.5, 0.5] and len(probes) == 3
     assert ok and h == pytest.approx(-b / (2 * a), rel=1e-12) and hmin == 0.5
+
+
+# ------------------------------------------------------------- heavy ball (eq. HB)
+
+def _hb_closed_form(lam, alpha, beta, e0, k):
+    """Component of the heavy-ball error after k steps on f = lam e^2 / 2:
+    e_{k+1} = (1 + beta - alpha lam) e_k - beta e_{k-1}, e_{-1} = e_0, solved
+    through the roots of z^2 - (1 + beta - alpha lam) z + beta = 0."""
+    a = 1.0 + beta - alpha * lam
+    disc = complex(a * a - 4.0 * beta)
+    r1, r2 = (a + disc ** 0.5) / 2.0, (a - disc ** 0.5) / 2.0
+    e1 = (1.0 - alpha * lam) * e0
+    if abs(r1 - r2) < 1e-12:                 # double root: e_k = (c1 + c2 k) r^k
+        c1 = e0
+        c2 = e1 / r1 - e0
+        return ((c1 + c2 * k) * r1 ** k).real
+    c2 = (e1 - r1 * e0) / (r2 - r1)
+    c1 = e0 - c2
+    return (c1 * r1 ** k + c2 * r2 ** k).real
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.08, 0.5), (0.15, 0.3), (0.05, 0.9)])
+def test_heavy_ball_follows_its_eigen_closed_form(alpha, beta):
+    lam = np.array([1.0, 4.0, 10.0])
+    x0 = np.array([1.0, -2.0, 0.5])
+    r = minimize(quad(lam, np.zeros(3)), x0,
+                 MinParams(method=oracle.HB, hb_alpha=alpha, hb_beta=beta, tol=1e-300, max_iter=40))
+    assert r.term == oracle.MAX_ITER and r.iters == 40 and r.evals == 41
+    for k, (f, h, ev) in enumerate(r.trace, start=1):
+        e = np.array([_hb_closed_form(l, alpha, beta, x, k) for l, x in zip(lam, x0)])
+        assert f == pytest.approx(0.5 * float(lam @ (e * e)), rel=1e-10, abs=1e-300)
+        assert h == alpha and ev == k + 1
+    e40 = np.array([_hb_closed_form(l, alpha, beta, x, 40) for l, x in zip(lam, x0)])
+    np.testing.assert_allclose(r.x, e40, rtol=1e-9, atol=1e-14)
+
+
+def test_heavy_ball_without_momentum_is_the_fixed_step_gradient_method():
+    lam = np.array([0.5, 2.0, 3.0])
+    x0 = np.array([3.0, 1.0, -1.0])
+    alpha = 0.3
+    r = minimize(quad(lam, np.zeros(3)), x0, MinParams(method=oracle.HB, hb_alpha=alpha, hb_beta=0.0,
+                                                        tol=1e-300, max_iter=25))
+    np.testing.assert_allclose(r.x, (1.0 - alpha * lam) ** 25 * x0, rtol=1e-12)
+
+
+def test_heavy_ball_reports_divergence():
+    def fg(x):
+        return float(np.sum(x ** 4)), 4.0 * x ** 3
+    with np.errstate(over="ignore", invalid="ignore"):
+        r = minimize(fg, np.array([2.0]), MinParams(method=oracle.HB, hb_alpha=1.0, hb_beta=0.0, max_iter=100))
+    assert r.term == oracle.DIVERGED and np.isfinite(r.f) and r.iters < 10
+
+
+def test_heavy_ball_needs_its_parameters():
+    with pytest.raises(ValueError):
+        minimize(quad(np.ones(2), np.zeros(2)), np.ones(2), MinParams(method=oracle.HB))
+
+
+# ------------------------------------------------ optimized gradient method (eq. optim)
+
+def test_ogm_t_sequence():
+    t = 1.0
+    t1 = oracle.ogm_t_next(t)
+    assert t1 == pytest.approx((1.0 + math.sqrt(5.0)) / 2.0, rel=1e-15)
+    for k in range(200):
+        tn = oracle.ogm_t_next(t)
+        assert tn * tn - tn == pytest.approx(t * t, rel=1e-13)
+        assert tn >= (k + 2) / 2.0
+        t = tn
+
+
+def _exact_step(A, x, d):
+    """x - h d with h minimizing x'Ax/2 along -d (closed form)."""
+    g = A @ x
+    return x - (float(g @ d) / float(d @ (A @ d))) * d
+
+
+def test_ogm_first_two_steps_by_hand_on_a_quadratic():
+    A = np.array([[3.0, 1.0, 0.0], [1.0, 2.0, 0.5], [0.0, 0.5, 1.0]])
+    x0 = np.array([1.0, -1.0, 2.0])
+    fg = quad(A, np.zeros(3))
+    # h_init = 0.5: the exact steps (1.10, then 0.06) lie inside LS_PAR's
+    # window [h1/100, 10 h1], so both line searches are exact on a quadratic
+    r = minimize(fg, x0, MinParams(method=oracle.OGM, tol=1e-300, max_iter=2, h_init=0.5))
+    assert r.iters == 2
+    # iteration 0: y = x0, d = (1 - 1/t1) g0 + (2/t1) g0, an exact step along -g0
+    t1 = (1.0 + math.sqrt(5.0)) / 2.0
+    g0 = A @ x0
+    x1 = _exact_step(A, x0, g0)
+    # iteration 1: anchor x0, gradient sum t0 g0 + t1 g1
+    t2 = 0.5 * (1.0 + math.sqrt(4.0 * t1 * t1 + 1.0))
+    g1 = A @ x1
+    y = (1.0 - 1.0 / t2) * x1 + x0 / t2
+    d = (1.0 - 1.0 / t2) * g1 + (2.0 / t2) * (g0 + t1 * g1)
+    x2 = _exact_step(A, y, d)
+    f = lambda x: 0.5 * float(x @ (A @ x))
+    assert r.trace[0][0] == pytest.approx(f(x1), rel=1e-11)
+    assert r.trace[1][0] == pytest.approx(f(x2), rel=1e-9)
+    np.testing.assert_allclose(r.x, x2, rtol=1e-8, atol=1e-12)
+    # two evaluations of the first iteration (LS_PAR), three of the second (y, two trials)
+    assert [e for _, _, e in r.trace] == [3, 6]
+
+
+def test_ogm_isotropic_quadratic_one_step():
+    x0 = np.array([3.0, -4.0, 1.0])
+    # the exact step |x0| = 5.1 lies in LS_PAR's window [h1/100, 10 h1] for h1 = 1
+    r = minimize(quad(np.full(3, 2.0), np.zeros(3)), x0, MinParams(method=oracle.OGM, tol=1e-9, h_init=1.0))
+    assert r.term == oracle.CONVERGED and r.iters == 1
+
+
+def test_ogm_converges_on_an_ill_conditioned_quadratic():
+    rng = np.random.default_rng(3)
+    lam = np.geomspace(1.0, 100.0, 60)
+    b = rng.normal(size=60)
+    r = minimize(quad(lam, b), np.zeros(60), MinParams(method=oracle.OGM, tol=1e-7, max_iter=2000))
+    assert r.term == oracle.CONVERGED
+    np.testing.assert_allclose(r.x, b / lam, rtol=0, atol=1e-6)
