@@ -103,7 +103,7 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     std::vector<SysInfo> sys(n_sys);
     int aoff = 0, uoff = 0, units = 0, chunks = 0, nbd = 0, nag = 0, ndh = 0, ebo = 0;
     size_t red = 0;
-    L.accept_bx = std::max(1, std::min(64, (3 * n_max + 8 * kFinBlock - 1) / (8 * kFinBlock)));
+    L.acc_rows = std::max(1, m_max + 1);
     for (int k = 0; k < n_sys; ++k) {
         SysInfo& si = sys[k];
         std::memset(&si, 0, sizeof si);
@@ -136,11 +136,11 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
         ebo += si.bonded_blocks;
         si.fin_blocks = (si.n + kTile - 1) / kTile;      // one finalize workgroup per tile
         si.vec_blocks = (3 * si.n + kFinBlock - 1) / kFinBlock;
+        si.acc_bx = std::max(1, std::min(64, (3 * si.n + 8 * kFinBlock - 1) / (8 * kFinBlock)));
         si.red0 = (int32_t)red;
-        red += std::max((size_t)si.fin_blocks * 4, (size_t)L.accept_bx * (kMaxM + 1) * 6);
-        L.max_fin_blocks = std::max(L.max_fin_blocks, si.fin_blocks);
-        L.max_vec_blocks = std::max(L.max_vec_blocks, si.vec_blocks);
-        L.max_bonded_blocks = std::max(L.max_bonded_blocks, si.bonded_blocks);
+        red += std::max((size_t)si.fin_blocks * 4, (size_t)si.acc_bx * L.acc_rows * 6);
+        L.n_vec_blocks += si.vec_blocks;
+        L.n_acc_blocks += si.acc_bx;
         aoff += si.np;
         uoff += si.n;
     }
@@ -190,6 +190,10 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.off_inc = take((size_t)L.n_terms_slots * 4);
     L.off_red = take(red * 8);
     L.off_vec = take((size_t)V_COUNT * L.vstride * 8 + (size_t)kTraceCap * 3 * 8);
+    L.off_map_fin = take((size_t)L.n_fin_blocks * 8);
+    L.off_map_vec = take((size_t)L.n_vec_blocks * 8);
+    L.off_map_bonded = take((size_t)L.n_bonded_blocks * 8);
+    L.off_map_acc = take((size_t)L.n_acc_blocks * 8);
     L.total = o;
     if (out) *out = std::move(sys);
     return true;
@@ -439,6 +443,20 @@ static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* work
     HIP_TRY(up(L.off_dihp, dihp.data(), dihp.size() * 8));
     HIP_TRY(up(L.off_inc_start, inc_start.data(), inc_start.size() * 4));
     HIP_TRY(up(L.off_inc, inc.data(), inc.size() * 4));
+    // flat grid maps: (system, local block) of every workgroup
+    {
+        std::vector<int32_t> mf, mv, mb, ma;
+        for (int k = 0; k < n_sys; ++k) {
+            for (int b = 0; b < sys[k].fin_blocks; ++b) { mf.push_back(k); mf.push_back(b); }
+            for (int b = 0; b < sys[k].vec_blocks; ++b) { mv.push_back(k); mv.push_back(b); }
+            for (int b = 0; b < sys[k].bonded_blocks; ++b) { mb.push_back(k); mb.push_back(b); }
+            for (int b = 0; b < sys[k].acc_bx; ++b) { ma.push_back(k); ma.push_back(b); }
+        }
+        HIP_TRY(up(L.off_map_fin, mf.data(), mf.size() * 4));
+        HIP_TRY(up(L.off_map_vec, mv.data(), mv.size() * 4));
+        HIP_TRY(up(L.off_map_bonded, mb.data(), mb.size() * 4));
+        HIP_TRY(up(L.off_map_acc, ma.data(), ma.size() * 4));
+    }
     Args a{};
     a.L = L;
     a.ws = ws;

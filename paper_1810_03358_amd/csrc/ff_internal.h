@@ -190,6 +190,7 @@ struct SysInfo {
     int32_t bond0, angle0, dih0;   // first bond / angle / torsion in the batch-wide arrays
     int32_t bonded_blocks, eb0;
     int32_t fin_blocks, vec_blocks;
+    int32_t acc_bx;       // accept-pass workgroups per product row
     int32_t red0;         // first double of this system's reduction partials
 };
 
@@ -198,8 +199,9 @@ struct Layout {
     int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;   // n, np: totals over the batch
     int32_t n_bonds, n_angles, n_dihedrals, n_terms_slots, n_bonded_blocks;
     int32_t n_fin_blocks;
-    int32_t max_fin_blocks, max_vec_blocks, max_bonded_blocks;   // per-system maxima (grid x-extents)
-    int32_t accept_bx;        // x-extent of the accept pass grid
+    // flat grids: workgroup b of a pass handles (system, local block) = map[b]
+    int32_t n_vec_blocks, n_acc_blocks;
+    int32_t acc_rows;         // y-extent of the accept grid: 1 + largest L-BFGS memory
     int32_t m_max;
     int32_t cfg;              // tile configuration index
     size_t vstride;           // doubles between vectors
@@ -211,6 +213,7 @@ struct Layout {
     size_t off_bond, off_bondp, off_angle, off_anglep, off_dih, off_dihp;
     size_t off_fb, off_eb, off_inc_start, off_inc;
     size_t off_red, off_vec;
+    size_t off_map_fin, off_map_vec, off_map_bonded, off_map_acc;   // int2 maps of the flat grids
     size_t total;
 };
 

@@ -221,18 +221,18 @@ __device__ __forceinline__ void gather_tile(const Args& a, const SysInfo& si, in
 // the tile (gather_tile) + the bonded-term slots of each atom (staged through
 // LDS, added in slot order).  Per-workgroup partials: max |g|, |g|^2,
 // optionally <g_base, d>, and a share of the pair-workgroup and bonded-block
-// energies (k_fin_reduce adds them up).  Grid: (largest per-system tile
-// count, 1, systems).
+// energies (k_fin_reduce adds them up).  Grid: every tile of every system
+// (flat, map_fin).
 __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     const Layout& L = a.L;
-    const int sys = blockIdx.z;
+    const int2 mb = at<int2>(a.ws, L.off_map_fin)[blockIdx.x];
+    const int sys = mb.x, blk = mb.y;                    // system and its tile
     const SysInfo si = sys_info(a)[sys];
-    if ((int)blockIdx.x >= si.fin_blocks) return;
     Ctl* c = ctl_at(a, sys);
     if (!a.direct && (c->action != ACT_EVAL || c->target < 0 || c->target >= kNumSlots)) return;
     double* G = a.direct ? (a.g_out ? a.g_out + 3 * (size_t)si.uoff : nullptr) : vec(a, V_G0 + c->target, si);
     const bool want_slope = !a.direct && c->want_slope;
-    const int t = si.aoff / kTile + blockIdx.x;          // global tile
+    const int t = si.aoff / kTile + blk;                 // global tile
     const int row = t * kTile / L.block;                 // its I-block
     __shared__ double tot[3 * kTile];
     __shared__ double fbv[kFinBlock][3];
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
         }
         __syncthreads();
     }
-    const int atom = blockIdx.x * kTile + (int)threadIdx.x;   // local atom
+    const int atom = blk * kTile + (int)threadIdx.x;          // local atom
     const bool real = threadIdx.x < kTile && atom < si.n;
     if (!real) gx = gy = gz = 0.0;
     if (real && G) { G[3 * (size_t)atom] = gx; G[3 * (size_t)atom + 1] = gy; G[3 * (size_t)atom + 2] = gz; }
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     }
     // this workgroup's share of the pair-workgroup and bonded-block energies
     {
-        const int nb = si.fin_blocks, b = blockIdx.x;
+        const int nb = si.fin_blocks, b = blk;
         const double* ep = at<double>(a.ws, L.off_ep) + si.chunk0;
         const double* eb = at<double>(a.ws, L.off_eb) + si.eb0;
         const int p0 = (int)((long long)si.n_chunks * b / nb), p1 = (int)((long long)si.n_chunks * (b + 1) / nb);
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     double tr[4];
     block_reduce<4>(v, true, tr);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) red[4 * blockIdx.x + k] = tr[k];
+        for (int k = 0; k < 4; ++k) red[4 * blk + k] = tr[k];
 }
 
 // Totals of one system's finalize partials in a fixed order, then E, the
@@ -345,7 +345,8 @@ __global__ void __launch_bounds__(kFinBlock) k_fin_reduce(Args a) {
 // trial, or the FGM momentum point.  Rounding is kept explicit (no
 // contraction) so that trial points are reproducible.
 __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
-    const int sys = blockIdx.z;
+    const int2 mb = at<int2>(a.ws, a.L.off_map_vec)[blockIdx.x];
+    const int sys = mb.x;
     const SysInfo si = sys_info(a)[sys];
     const Ctl* c = ctl_at(a, sys);
     if (c->action != ACT_EVAL || c->point_mode == PM_USE) return;
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
     const int pm = c->point_mode;
     if ((pm == PM_MOMENTUM || pm == PM_HB || pm == PM_OGM_Y) && (c->prev < 0 || c->prev >= kNumSlots)) return;
     const int n3 = 3 * si.n;
-    const int i = blockIdx.x * kFinBlock + threadIdx.x;
+    const int i = mb.y * kFinBlock + threadIdx.x;
     if (i >= n3) return;
     double* xt = vec(a, V_X0 + c->target, si);
     const double* xb = vec(a, V_X0 + c->base, si);
@@ -394,26 +395,28 @@ __global__ void __launch_bounds__(kFinBlock) k_prepare(Args a) {
 //          history vectors), <s,y> <y,y> <s,s> <g,s> <g,y> <g,g> and, for
 //          the pair in every occupied history slot q, <s,S_q> <s,Y_q>
 //          <y,S_q> <y,Y_q> <g,S_q> <g,Y_q>.
-// Grid: (accept_bx, kMaxM + 1, systems).  Row 0 computes the first group of
-// six, row r >= 1 the six products with the pair in slot r-1 (s and y are
-// recomputed from the point vectors in every row, with the same arithmetic);
-// each workgroup strides over its share of the 3N elements and writes one
-// partial per product (k_accept_reduce adds them up in workgroup order).
+// Grid: (accept workgroups of every system (flat, map_acc), 1 + largest
+// L-BFGS memory).  Row 0 computes the first group of six, row r >= 1 the six
+// products with the pair in slot r-1 (s and y are recomputed from the point
+// vectors in every row, with the same arithmetic); each workgroup strides over
+// its share of the 3N elements and writes one partial per product
+// (k_accept_reduce adds them up in workgroup order).
 __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
-    const int sys = blockIdx.z;
+    const int2 mb = at<int2>(a.ws, a.L.off_map_acc)[blockIdx.x];
+    const int sys = mb.x, bx = mb.y;
     const SysInfo si = sys_info(a)[sys];
     Ctl* c = ctl_at(a, sys);
     if (!c->accept) return;
     const int n3 = 3 * si.n;
     const int method = c->p.method;
     const int row = blockIdx.y;
-    // acc_rows is fixed while this pass runs (the last workgroup changes
-    // hist_n, and a workgroup without work may start after that)
+    // acc_rows is fixed while this pass runs (the reduce kernel changes
+    // hist_n afterwards)
     const int rows = c->acc_rows;
     const int nh = method == M_LBFGS ? rows - 1 : 0;
     const bool active = row < rows;
     double* red = at<double>(a.ws, a.L.off_red) + si.red0;
-    const int nbx = gridDim.x;
+    const int nbx = si.acc_bx;
     if (active) {
         double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const double* xn = vec(a, V_X0 + c->acc_new, si);
@@ -426,7 +429,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
             const double* src = c->ogm_s_anchor ? vec(a, V_G0 + c->prev_x, si) : vec(a, V_R, si);
             double* S = vec(a, V_R, si);
             const double t = c->ogm_t_next;
-            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+            for (int i = bx * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 const double sn = __dadd_rn(src[i], __dmul_rn(t, gn[i]));
                 S[i] = sn;
                 v[0] += gn[i] * sn;
@@ -434,7 +437,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
             }
         } else if (method == M_CG) {
             const double* r = vec(a, V_R, si);
-            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+            for (int i = bx * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 v[0] += gn[i] * go[i];
                 v[1] += gn[i] * r[i];
                 v[2] += r[i] * go[i];
@@ -442,7 +445,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
         } else if (row == 0) {
             double* ss = vec(a, c->spare_s, si);
             double* yy = vec(a, c->spare_y, si);
-            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+            for (int i = bx * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 const double s = __dsub_rn(xn[i], xo[i]);
                 const double g = gn[i];
                 const double y = __dsub_rn(g, go[i]);
@@ -454,7 +457,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
         } else {
             const double* S = vec(a, c->hist_s[row - 1], si);
             const double* Y = vec(a, c->hist_y[row - 1], si);
-            for (int i = blockIdx.x * kFinBlock + threadIdx.x; i < n3; i += stride) {
+            for (int i = bx * kFinBlock + threadIdx.x; i < n3; i += stride) {
                 const double s = __dsub_rn(xn[i], xo[i]);
                 const double g = gn[i];
                 const double y = __dsub_rn(g, go[i]);
@@ -466,7 +469,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
         double tot[6];
         block_reduce<6>(v, false, tot);
         if (threadIdx.x == 0)
-            for (int k = 0; k < 6; ++k) red[((size_t)row * nbx + blockIdx.x) * 6 + k] = tot[k];
+            for (int k = 0; k < 6; ++k) red[((size_t)row * nbx + bx) * 6 + k] = tot[k];
     }
 }
 
@@ -480,7 +483,7 @@ __global__ void __launch_bounds__(kFinBlock) k_accept_reduce(Args a) {
     if (!c->accept) return;
     const int method = c->p.method;
     const int rows = c->acc_rows;
-    const int nbx = a.L.accept_bx;
+    const int nbx = si.acc_bx;
     const double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     __shared__ double dots[kMaxDots];
     const int nd = method == M_LBFGS || method == M_OGM ? 6 * rows : (method == M_CG ? 3 : 0);
@@ -589,16 +592,16 @@ __global__ void k_reset_ctl(Args a) {
 }
 
 hipError_t launch_finalize(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(a.L.max_fin_blocks, 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(a.L.n_fin_blocks), dim3(kFinBlock), 0, s, a);
     hipLaunchKernelGGL(k_fin_reduce, dim3(a.L.n_sys), dim3(kFinBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s) {
     if (which == 0)
-        hipLaunchKernelGGL(k_prepare, dim3(a.L.max_vec_blocks, 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
+        hipLaunchKernelGGL(k_prepare, dim3(a.L.n_vec_blocks), dim3(kFinBlock), 0, s, a);
     else {
-        hipLaunchKernelGGL(k_accept, dim3(a.L.accept_bx, kMaxM + 1, a.L.n_sys), dim3(kFinBlock), 0, s, a);
+        hipLaunchKernelGGL(k_accept, dim3(a.L.n_acc_blocks, a.L.acc_rows), dim3(kFinBlock), 0, s, a);
         hipLaunchKernelGGL(k_accept_reduce, dim3(a.L.n_sys), dim3(kFinBlock), 0, s, a);
     }
     return hipGetLastError();

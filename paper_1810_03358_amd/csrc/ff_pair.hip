@@ -182,13 +182,13 @@ __device__ void bonded_block(const Args& a, const double* X, const SysInfo& si, 
 }
 
 // Bonded terms of one evaluation (any precision mode: always FP64).
-// Grid: (largest per-system block count, 1, systems).
+// Grid: every bonded block of every system (flat, map_bonded).
 __global__ void __launch_bounds__(kBondedPerBlock) k_bonded(Args a) {
-    const int sys = blockIdx.z;
+    const int2 m = at<int2>(a.ws, a.L.off_map_bonded)[blockIdx.x];
+    const int sys = m.x;
     const SysInfo si = sys_info(a)[sys];
-    if ((int)blockIdx.x >= si.bonded_blocks) return;
     if (!(eval_active(a, sys, 0) || eval_active(a, sys, 1))) return;
-    bonded_block(a, eval_coords(a, sys, si), si, blockIdx.x, kBondedPerBlock);
+    bonded_block(a, eval_coords(a, sys, si), si, m.y, kBondedPerBlock);
 }
 
 // ---------------------------------------------------------------- FP32 pairs
@@ -591,7 +591,7 @@ hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
 }
 
 hipError_t launch_bonded(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bonded, dim3(a.L.max_bonded_blocks, 1, a.L.n_sys), dim3(kBondedPerBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bonded, dim3(a.L.n_bonded_blocks), dim3(kBondedPerBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -45,7 +45,10 @@ def test_workspace_bytes_grows_with_size(n):
     s = make_system(np_zeros(n))
     b0 = ff.workspace_bytes(s, 0)
     assert b0 > 0 and b0 % 256 == 0
-    assert ff.workspace_bytes(s, 10) == b0      # vectors are sized for the largest memory
+    # the vectors are sized for the largest memory; only the accept pass's
+    # reduction rows (1 + m) grow with m
+    b10 = ff.workspace_bytes(s, 10)
+    assert b0 <= b10 <= b0 + 64 * 11 * 6 * 8 + 256
 
 
 def np_zeros(n):
