@@ -232,6 +232,15 @@ ff_status ff_minimize(ff_ctx *ctx, double *xyz_inout, const ff_min_params *param
  * written or a negative ff_status.  Blocks on `stream`. */
 int32_t ff_get_trace(ff_ctx *ctx, double *host_out, int32_t max_entries, void *stream);
 
+/* Diagnostic of section 3 (the non-convexity of the problem near the start):
+ * the energy along the unit antigradient at xyz (device, concatenated [n][3]),
+ *   e_out[k * n_sys + s] = E_s(x_s + t[k] u_s),  u_s = -grad E_s(x_s) / |grad E_s(x_s)|
+ * (u_s = 0 if the gradient is zero), for k < n_t <= 4096; t and e_out are HOST
+ * arrays, t finite (negative values step uphill).  Uses the context's vector
+ * workspace, so a following ff_minimize cannot resume.  Blocks until done. */
+ff_status ff_energy_profile(ff_ctx *ctx, const double *xyz, const double *t, int32_t n_t,
+                            double *e_out, int32_t precision, void *stream);
+
 /* Measurement helper: average duration in milliseconds of `reps`
  * back-to-back launches of the nonbonded pair kernel alone at xyz (device),
  * timed with HIP events recorded on `stream`.  Overwrites the workspace's

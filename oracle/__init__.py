@@ -13,7 +13,8 @@ shares no code with the HIP path.
   section 4) and L-BFGS (Algorithms 3 and 4), heavy ball (eq. HB) and the
   optimized gradient method (eq. optim), in the paper's order and notation.
 """
-from .energy import System, energy_grad, energy_terms, atom_gradients, num_threads, build  # noqa: F401
+from .energy import (System, energy_grad, energy_terms, atom_gradients, num_threads, build,  # noqa: F401
+                     energy_profile)
 from .minimize import (  # noqa: F401
     MinParams, MinResult, minimize, ls_par, ls_h, lbfgs_direction, fgm_coefficients, ogm_t_next,
     GD, FGM, CG, LBFGS, HB, OGM, LS_PAR, LS_H, cg_beta,

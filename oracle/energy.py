@@ -125,3 +125,15 @@ def atom_gradients(sys, x, atoms):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def energy_profile(system, x, t):
+    """E(x + t u) for every t, u = -grad E(x)/|grad E(x)| the unit antigradient
+    at x (u = 0 if the gradient vanishes): the one-dimensional slice the paper
+    uses to show how non-convex the energy is near a start point (section 3)."""
+    sysc = system if isinstance(system, System) else System(system)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    _, g = energy_grad(sysc, x)
+    nrm = float(np.linalg.norm(g))
+    u = -g / nrm if nrm > 0.0 else np.zeros_like(g)
+    return np.array([energy_grad(sysc, x + tk * u)[0] for tk in np.asarray(t, dtype=np.float64).ravel()])

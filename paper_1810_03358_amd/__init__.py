@@ -208,6 +208,18 @@ class Context:
                     evals_fp64=r.evals_fp64, energy=r.energy, grad_inf=r.grad_inf, grad_2=r.grad_2) for r in res]
         return out if self.is_batch else out[0]
 
+    def energy_profile(self, x: torch.Tensor, t, precision: str | int = "fp64", stream=None) -> np.ndarray:
+        """E(x + t u) along the unit antigradient u at x for every t:
+        array [len(t)] (a batch: [len(t), n_sys])."""
+        x = self._coords(x)
+        tv = np.ascontiguousarray(np.asarray(t, dtype=np.float64).ravel())
+        out = np.empty((len(tv), self.n_sys), dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        _check(N.load().ff_energy_profile(self._ctx, C.c_void_p(x.data_ptr()), tv.ctypes.data_as(dp), len(tv),
+                                          out.ctypes.data_as(dp), int(PRECISIONS.get(precision, precision)),
+                                          _stream_ptr(stream)), "ff_energy_profile")
+        return out if self.is_batch else out[:, 0]
+
     def time_pair(self, x: torch.Tensor, precision: str | int = "fp32", reps: int = 20, stream=None) -> float:
         """Average duration (ms) of the pair kernel alone at x, HIP-event timed."""
         x = self._coords(x)

@@ -49,7 +49,7 @@ class FFMinResult(C.Structure):
 EXPORTS = ("ff_workspace_bytes", "ff_workspace_bytes_batch", "ff_create", "ff_create_batch", "ff_batch_size",
            "ff_destroy", "ff_energy_grad", "ff_minimize", "ff_get_trace", "ff_time_pair", "ff_default_params",
            "ff_last_error", "ff_num_tile_configs", "ff_tile_config_info", "ff_workspace_bytes_tiled",
-           "ff_create_tiled", "ff_get_tiling", "ff_autotune_workspace_bytes", "ff_autotune")
+           "ff_create_tiled", "ff_get_tiling", "ff_autotune_workspace_bytes", "ff_autotune", "ff_energy_profile")
 
 _lib = None
 
@@ -104,6 +104,8 @@ def load():
     lib.ff_autotune.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
                                 C.c_int32, C.c_void_p, _ip, _ip, _dp]
     lib.ff_autotune.restype = C.c_int
+    lib.ff_energy_profile.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int32, _dp, C.c_int32, C.c_void_p]
+    lib.ff_energy_profile.restype = C.c_int
     lib.ff_last_error.argtypes = []
     lib.ff_last_error.restype = C.c_char_p
     _lib = lib

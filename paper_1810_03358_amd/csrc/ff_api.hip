@@ -28,6 +28,8 @@ hipError_t launch_pair(const Args& a, int prec, hipStream_t s);
 hipError_t launch_bonded(const Args& a, hipStream_t s);
 hipError_t launch_finalize(const Args& a, hipStream_t s);
 hipError_t launch_cycle_vec(const Args& a, int which, hipStream_t s);
+hipError_t launch_profile_point(const Args& a, const double* x, const double* g, const double* g2, double t,
+                                double* xt, hipStream_t s);
 hipError_t launch_kick(const Args& a, const MinParamsDev& p, int resume, double* trace, int trace_cap,
                        hipStream_t s);
 hipError_t launch_reset(const Args& a, hipStream_t s);
@@ -744,6 +746,52 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
 
 // Average duration (ms) of `reps` back-to-back launches of the pair kernel
 // alone at xyz (all systems), timed with HIP events recorded on the launch stream.
+ff_status ff_energy_profile(ff_ctx* c, const double* xyz, const double* t, int32_t n_t, double* e_out,
+                            int32_t precision, void* stream) {
+    g_err.clear();
+    if (!c || !xyz || !t || !e_out) return fail(FF_ERR_ARG, "null argument");
+    if (n_t < 1 || n_t > kMaxProfile) return fail(FF_ERR_ARG, "n_t must be in [1, %d]", kMaxProfile);
+    if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
+    for (int k = 0; k < n_t; ++k)
+        if (!std::isfinite(t[k])) return fail(FF_ERR_ARG, "t[%d] is not finite", k);
+    hipStream_t st = stream ? (hipStream_t)stream : c->own;
+    const Layout& L = c->L;
+    // scratch in the optimizer's vector region: g, x_t ([n][3] each), |g|^2
+    // and the energies ([n_sys] per point)
+    double* base = at<double>(c->ws, L.off_vec);
+    const size_t n3 = 3 * (size_t)L.n;
+    double* g = base;
+    double* xt = base + n3;
+    double* g2 = base + 2 * n3;
+    double* e = g2 + L.n_sys;
+    Args a{};
+    a.L = L;
+    a.ws = c->ws;
+    a.direct = 1;
+    a.direct_prec = precision;
+    a.xyz_in = xyz;
+    a.e_out = e;                 // scratch for E(x) itself
+    a.g_out = g;
+    a.g2_out = g2;
+    HIP_TRY(launch_bonded(a, st));
+    HIP_TRY(launch_pair(a, precision, st));
+    HIP_TRY(launch_finalize(a, st));
+    a.xyz_in = xt;
+    a.g_out = nullptr;
+    a.g2_out = nullptr;
+    for (int k = 0; k < n_t; ++k) {
+        a.e_out = e + (size_t)(k + 1) * L.n_sys;
+        HIP_TRY(launch_profile_point(a, xyz, g, g2, t[k], xt, st));
+        HIP_TRY(launch_bonded(a, st));
+        HIP_TRY(launch_pair(a, precision, st));
+        HIP_TRY(launch_finalize(a, st));
+    }
+    HIP_TRY(hipMemcpyAsync(e_out, e + L.n_sys, (size_t)n_t * L.n_sys * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    c->last_method = -1;         // the vectors a resumed minimization needs are gone
+    return FF_OK;
+}
+
 ff_status ff_time_pair(ff_ctx* c, const double* xyz, int32_t precision, int32_t reps, void* stream,
                        double* avg_ms) {
     g_err.clear();

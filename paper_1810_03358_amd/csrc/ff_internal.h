@@ -29,6 +29,7 @@ constexpr int kMaxLsTrials = 8;
 constexpr int kBondedPerBlock = 256;  // bonded terms per workgroup
 constexpr int kTraceCap = 4096;       // per-iteration trace entries kept
 constexpr int kMaxChunk = 4096;       // j-tiles per pair workgroup, upper bound
+constexpr int kMaxProfile = 4096;     // points of one energy profile
 
 // Distances (A^2) below which the FP32 pair path first corrects the
 // displacement with the low halves of the double-single coordinates and,
@@ -225,6 +226,7 @@ struct Args {
     const double* xyz_in;    // direct mode: coordinates, [sum n][3] over the batch
     double* e_out;           // direct mode: energies [n_sys]
     double* g_out;           // direct mode: gradient [sum n][3] or null
+    double* g2_out;          // direct mode: |grad E|^2 per system, or null
     int32_t direct;          // 1: ff_energy_grad, 0: optimizer cycle
     int32_t direct_prec;
 };

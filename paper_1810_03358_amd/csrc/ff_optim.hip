@@ -329,6 +329,7 @@ __global__ void __launch_bounds__(kFinBlock) k_fin_reduce(Args a) {
     const double E = gt[3];
     if (a.direct) {
         if (a.e_out) a.e_out[sys] = E;
+        if (a.g2_out) a.g2_out[sys] = gt[1];
         return;
     }
     const int tg = c->target;
@@ -589,6 +590,27 @@ __global__ void k_reset_ctl(Args a) {
     c->done = 1;
     c->phase = PH_IDLE;
     c->iters = 0;
+}
+
+// Point of the energy profile: x + t u with u = -g / |g| per system (u = 0
+// where g = 0), all in the caller's concatenated layout.  Grid: flat over
+// every system's 3n elements (map_vec).
+__global__ void __launch_bounds__(kFinBlock) k_profile_point(Args a, const double* x, const double* g,
+                                                             const double* g2, double t, double* xt) {
+    const int2 mb = at<int2>(a.ws, a.L.off_map_vec)[blockIdx.x];
+    const SysInfo si = sys_info(a)[mb.x];
+    const int i = mb.y * kFinBlock + threadIdx.x;
+    if (i >= 3 * si.n) return;
+    const size_t o = 3 * (size_t)si.uoff + i;
+    const double nrm = sqrt(g2[mb.x]);
+    const double u = nrm > 0.0 ? __ddiv_rn(-g[o], nrm) : 0.0;
+    xt[o] = __dadd_rn(x[o], __dmul_rn(t, u));
+}
+
+hipError_t launch_profile_point(const Args& a, const double* x, const double* g, const double* g2, double t,
+                                double* xt, hipStream_t s) {
+    hipLaunchKernelGGL(k_profile_point, dim3(a.L.n_vec_blocks), dim3(kFinBlock), 0, s, a, x, g, g2, t, xt);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Args& a, hipStream_t s) {

@@ -150,3 +150,11 @@ def test_create_tiled_rejects_bad_tiling_before_touching_the_device():
     assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 99, 4, None, C.byref(ctx)) == ff.FF_ERR_ARG
     assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 0, 0, None, C.byref(ctx)) == ff.FF_ERR_ARG
     assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1024, 10, 0, 4, None, C.byref(ctx)) == ff.FF_ERR_WORKSPACE
+
+
+def test_energy_profile_rejects_bad_arguments_on_the_host():
+    lib = N.load()
+    t = (C.c_double * 2)(0.0, float("nan"))
+    out = (C.c_double * 2)()
+    ctx = C.c_void_p(0)
+    assert lib.ff_energy_profile(ctx, C.c_void_p(256), t, 2, out, 0, None) == ff.FF_ERR_ARG

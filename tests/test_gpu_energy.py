@@ -205,3 +205,34 @@ def test_rigid_motion_invariance_on_gpu():
     assert e2 == pytest.approx(e1, rel=1e-10)
     assert np.abs(g2 - g1 @ R.T).max() <= 1e-9 * np.abs(g1).max()
     assert np.abs(g1.sum(0)).max() <= 1e-10 * np.abs(g1).sum()
+
+
+# ---------------------------------------------- energy profile (section 3)
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_energy_profile_matches_the_oracle(prec):
+    s = config_system("chain512")
+    t = np.array([-0.02, 0.0, 0.01, 0.05, 0.2, 1.0, 3.0])
+    ref = oracle.energy_profile(s, s["x"], t)
+    ctx = ff.Context(s, m_max=0)
+    x = torch.tensor(s["x"], dtype=torch.float64, device="cuda")
+    print("profile chain512", prec, flush=True)
+    e = ctx.energy_profile(x, t, prec)
+    np.testing.assert_allclose(e, ref, rtol=1e-9 if prec == "fp64" else 1e-6)
+    # the profile is a slice of the clash-dominated start: it falls by orders
+    # of magnitude within an angstrom (the non-convexity the paper shows)
+    assert e[1] > 1e12 and e[5] < 1e-3 * e[1]
+
+
+def test_energy_profile_batch_and_degenerate_systems():
+    systems = [chain_system(200, 5), make_system([[1.0, 2.0, 3.0]], sigma=[3.0], eps=[0.2], q=[0.4]),
+               torsion_chain(90, 2)]
+    t = [0.0, 0.1, -0.1]
+    ctx = ff.Context(systems, m_max=0)
+    x = torch.tensor(np.concatenate([s["x"] for s in systems]), dtype=torch.float64, device="cuda")
+    print("profile batch", flush=True)
+    e = ctx.energy_profile(x, t, "fp64")
+    assert e.shape == (3, 3)
+    for k, s in enumerate(systems):
+        np.testing.assert_allclose(e[:, k], oracle.energy_profile(s, s["x"], t), rtol=1e-9, atol=1e-12)
+    np.testing.assert_array_equal(e[:, 1], np.zeros(3))

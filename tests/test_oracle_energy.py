@@ -268,3 +268,35 @@ def test_bad_index_rejected():
     s = make_system([[0, 0, 0], [1, 0, 0]], bonds=[[0, 2]], bond_k=[1], bond_r0=[1])
     with pytest.raises(ValueError):
         oracle.energy_grad(s, s["x"])
+
+
+# ------------------------------------------------ energy profile (section 3)
+
+@pytest.mark.parametrize("r0", [2.8, 3.2, 4.5])
+def test_profile_of_two_atoms_is_the_lj_curve(r0):
+    """Two LJ atoms on the x axis: the unit antigradient moves each one by
+    t/sqrt(2) along the axis, so the separation is r0 + sqrt(2) t on the
+    repulsive side (r0 < 2^(1/6) sigma) and r0 - sqrt(2) t on the attractive
+    one."""
+    sig, eps = 3.4, 0.2
+    s = make_system([[0, 0, 0], [r0, 0, 0]], sigma=[sig, sig], eps=[eps, eps])
+    t = np.array([-0.3, 0.0, 0.05, 0.2, 0.7])
+    e = oracle.energy_profile(s, s["x"], t)
+    sign = 1.0 if r0 < 2 ** (1 / 6) * sig else -1.0
+    r = r0 + sign * math.sqrt(2.0) * t
+    lj = 4 * eps * ((sig / r) ** 12 - (sig / r) ** 6)
+    np.testing.assert_allclose(e, lj, rtol=1e-12)
+
+
+def test_profile_slope_at_zero_is_minus_the_gradient_norm():
+    s = torsion_chain(40, 3)
+    _, g = oracle.energy_grad(s, s["x"])
+    h = 1e-5
+    e = oracle.energy_profile(s, s["x"], [-h, 0.0, h])
+    assert (e[2] - e[0]) / (2 * h) == pytest.approx(-np.linalg.norm(g), rel=1e-6)
+    assert e[1] == pytest.approx(oracle.energy_grad(s, s["x"])[0], rel=1e-15)
+
+
+def test_profile_with_a_zero_gradient_stays_put():
+    s = make_system([[1.0, 2.0, 3.0]], sigma=[3.0], eps=[0.2], q=[0.4])
+    np.testing.assert_array_equal(oracle.energy_profile(s, s["x"], [-1.0, 0.0, 2.5]), np.zeros(3))
