@@ -89,8 +89,7 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.n_sys = n_sys;
     if (n_sys > 1) { L.cfg = 0; L.chunk = 4; }
     else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
-    else if (n_max <= 16384) { L.cfg = 1; L.chunk = 4; }
-    else { L.cfg = 3; L.chunk = 8; }
+    else { L.cfg = 4; L.chunk = 2; }
     if (cfg_req >= 0) {
         if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk) return false;
         L.cfg = cfg_req;
