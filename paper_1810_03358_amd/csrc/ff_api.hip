@@ -621,6 +621,8 @@ ff_status ff_energy_grad(ff_ctx* c, const double* xyz, double* energy, double* g
     return FF_OK;
 }
 
+static constexpr int kCyclesPerGraph = 4;
+
 static ff_status build_graph(ff_ctx* c) {
     hipStream_t st = c->own;
     Args a{};
@@ -628,12 +630,16 @@ static ff_status build_graph(ff_ctx* c) {
     a.ws = c->ws;
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_cycle_vec(a, 0, st);
-    if (e == hipSuccess) e = launch_bonded(a, st);
-    if (e == hipSuccess) e = launch_pair(a, 1, st);
-    if (e == hipSuccess) e = launch_pair(a, 0, st);
-    if (e == hipSuccess) e = launch_finalize(a, st);
-    if (e == hipSuccess) e = launch_cycle_vec(a, 1, st);
+    // several cycles per graph: each graph launch costs a few us of its own
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kCyclesPerGraph && e == hipSuccess; ++k) {
+        e = launch_cycle_vec(a, 0, st);
+        if (e == hipSuccess) e = launch_bonded(a, st);
+        if (e == hipSuccess) e = launch_pair(a, 1, st);
+        if (e == hipSuccess) e = launch_pair(a, 0, st);
+        if (e == hipSuccess) e = launch_finalize(a, st);
+        if (e == hipSuccess) e = launch_cycle_vec(a, 1, st);
+    }
     hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return fail(FF_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(FF_ERR_HIP, "graph capture end: %s", hipGetErrorString(e2));
@@ -708,7 +714,7 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     // poll (n_done, evals) of the batch
     const char* dev_state = c->ws + L.off_batch;
     uint32_t* hs = (uint32_t*)c->host_flag;
-    int batch = 4;
+    int batch = 1;              // graph launches (kCyclesPerGraph cycles each) between polls
     uint32_t last_evals = 0xffffffffu;
     for (;;) {
         for (int k = 0; k < batch; ++k) HIP_TRY(hipGraphLaunch(c->graph, st));
@@ -719,7 +725,7 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
         // cycles without a new evaluation means the decision logic stopped
         if (hs[1] == last_evals) return fail(FF_ERR_HIP, "minimizer stalled (%u of %d systems done)", hs[0], L.n_sys);
         last_evals = hs[1];
-        batch = std::min(batch * 2, 64);
+        batch = std::min(batch * 2, 64 / kCyclesPerGraph);
     }
     for (int k = 0; k < L.n_sys; ++k) {
         const SysInfo& si = c->sys[k];

@@ -493,9 +493,8 @@ __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const d
 }
 
 template <int WAVES, int IPL>
-__global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
+__device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
     const Layout& L = a.L;
-    const int wg = blockIdx.x;
     const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
     if (!eval_active(a, ch.sys, 0)) return;
     const SysInfo si = sys_info(a)[ch.sys];
@@ -567,6 +566,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
     block_energy_store<WAVES>(e, at<double>(a.ws, L.off_ep) + wg);
 }
 
+// The FP64 kernel walks the chunks with a grid stride: in FP32 mode (and in
+// cycles without an evaluation) its workgroups only check and exit, and a
+// capped grid keeps that cheap.
+constexpr int kPair64Grid = 4096;
+
+template <int WAVES, int IPL>
+__global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
+    // one system: a single activity check for the whole launch; a batch
+    // checks the system of every chunk
+    if (a.L.n_sys == 1 && !eval_active(a, 0, 0)) return;
+    for (int wg = blockIdx.x; wg < a.L.n_chunks; wg += gridDim.x) pair64_chunk<WAVES, IPL>(a, wg);
+}
+
 // ------------------------------------------------------------- host launch
 // Tile configurations (index = Layout::cfg): I-block of B = 64 * waves * ipl
 // atoms.  Both precisions use the same B so that they share one chunk table.
@@ -574,7 +586,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
     case ID: {                                                                                     \
         constexpr TileConfig T = kTileConfigs[ID];                                                 \
         if (prec) hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
-        else hipLaunchKernelGGL((k_pair64<T.waves64, T.ipl64>), dim3(grid), dim3(64 * T.waves64), 0, s, a);     \
+        else hipLaunchKernelGGL((k_pair64<T.waves64, T.ipl64>), dim3(grid < kPair64Grid ? grid : kPair64Grid), \
+                                dim3(64 * T.waves64), 0, s, a);                                                 \
         break;                                                                                     \
     }
 
