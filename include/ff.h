@@ -91,8 +91,9 @@ typedef enum { FF_LS_DEFAULT = -1, FF_LS_PAR = 0, FF_LS_H = 1 } ff_linesearch;
 /* System description: HOST pointers, read only during ff_create.
  * Angles are (i, vertex, k).  Excluded pairs are the bonded pairs and the
  * outer atoms of every angle; 1-4 pairs interact at full strength; there is
- * no cutoff.  This build requires every excluded pair (i, j) to satisfy
- * |i - j| <= 64 (FF_ERR_UNSUPPORTED otherwise). */
+ * no cutoff.  Any topology is accepted: excluded pairs up to 64 atoms apart in
+ * index use a per-atom bitmask, farther ones (cross-links, ring closures)
+ * per-tile masks (a slightly slower pair kernel is used for such systems). */
 typedef struct {
     int32_t n_atoms;
     const double *q, *sigma, *eps;                      /* [n_atoms] e, A, kcal/mol */

@@ -11,6 +11,7 @@
 // control block says so).  The host replays the graph and polls the number of
 // finished systems.
 #include <algorithm>
+#include <utility>
 #include <cstdarg>
 #include <cstddef>
 #include <cmath>
@@ -69,6 +70,33 @@ static ff_status fail(ff_status st, const char* fmt, ...) {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ layout
+// Excluded pairs (1-2 and 1-3) of one system that are more than kExclWindow
+// atoms apart, as (lower, higher) global padded indices.  Pairs with a bad
+// index or null arrays are skipped here (validation reports them).
+static void far_exclusions(const ff_system& s, int aoff, std::vector<std::pair<int, int>>& out) {
+    const int n = s.n_atoms;
+    auto add = [&](int i, int j) {
+        if (i < 0 || j < 0 || i >= n || j >= n || i == j) return;
+        const int lo = std::min(i, j), hi = std::max(i, j);
+        if (hi - lo > kExclWindow) out.emplace_back(aoff + lo, aoff + hi);
+    };
+    if (s.bond)
+        for (int b = 0; b < s.n_bonds; ++b) add(s.bond[2 * b], s.bond[2 * b + 1]);
+    if (s.angle)
+        for (int a = 0; a < s.n_angles; ++a) add(s.angle[3 * a], s.angle[3 * a + 2]);
+}
+
+// Distinct pair units (I-block of the lower atom, j-tile of the higher one)
+// of a list of far exclusions, as sorted (row << 32 | tile) keys.
+static std::vector<long long> far_unit_keys(const std::vector<std::pair<int, int>>& far, int block) {
+    std::vector<long long> keys;
+    keys.reserve(far.size());
+    for (auto& p : far) keys.push_back(((long long)(p.first / block) << 32) | (long long)(p.second / kTile));
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    return keys;
+}
+
 // Tile configuration: explicit (cfg >= 0, chunk >= 1), or by default a single
 // system picks its I-block by size and a batch of several systems uses 64-atom
 // I-blocks so that small systems are padded to a multiple of 64 only
@@ -158,6 +186,11 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.n_bonded_blocks = ebo;
     L.n_fin_blocks = 0;
     for (auto& si : sys) L.n_fin_blocks += si.fin_blocks;
+    {
+        std::vector<std::pair<int, int>> far;
+        for (int k = 0; k < n_sys; ++k) far_exclusions(s[k], sys[k].aoff, far);
+        L.n_far_units = (int32_t)far_unit_keys(far, L.block).size();
+    }
     L.m_max = m_max;
     L.vstride = (3 * (size_t)L.np + 31) / 32 * 32;
     L.ctl_stride = align256(sizeof(Ctl));
@@ -195,6 +228,8 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.off_map_vec = take((size_t)L.n_vec_blocks * 8);
     L.off_map_bonded = take((size_t)L.n_bonded_blocks * 8);
     L.off_map_acc = take((size_t)L.n_acc_blocks * 8);
+    L.off_far_unit = take((size_t)L.n_units * 4);
+    L.off_far_mask = take((size_t)L.n_far_units * L.block * 8);
     L.total = o;
     if (out) *out = std::move(sys);
     return true;
@@ -221,10 +256,7 @@ static ff_status validate_system(const ff_system* s, int k, std::vector<uint64_t
     auto add_excl = [&](int i, int j) -> ff_status {
         if (i == j) return fail(FF_ERR_ARG, "system %d: a bond or angle joins atom %d to itself", k, i);
         const int lo = std::min(i, j), hi = std::max(i, j);
-        if (hi - lo > kExclWindow)
-            return fail(FF_ERR_UNSUPPORTED, "system %d: excluded pair (%d, %d) is more than %d atoms apart", k, lo, hi,
-                        kExclWindow);
-        excl[aoff + lo] |= 1ull << (hi - lo - 1);
+        if (hi - lo <= kExclWindow) excl[aoff + lo] |= 1ull << (hi - lo - 1);   // farther: far-unit masks
         return FF_OK;
     };
     for (int b = 0; b < s->n_bonds; ++b) {
@@ -444,6 +476,25 @@ static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* work
     HIP_TRY(up(L.off_dihp, dihp.data(), dihp.size() * 8));
     HIP_TRY(up(L.off_inc_start, inc_start.data(), inc_start.size() * 4));
     HIP_TRY(up(L.off_inc, inc.data(), inc.size() * 4));
+    // far exclusions: per-unit index and per-(unit, i-atom) masks over the j-tile
+    {
+        std::vector<std::pair<int, int>> far;
+        for (int k = 0; k < n_sys; ++k) far_exclusions(systems[k], sys[k].aoff, far);
+        const std::vector<long long> keys = far_unit_keys(far, L.block);
+        std::vector<int32_t> fu(L.n_units, -1);
+        std::vector<uint64_t> fm((size_t)keys.size() * L.block, 0ull);
+        for (size_t q = 0; q < keys.size(); ++q) {
+            const int row = (int)(keys[q] >> 32), t = (int)(keys[q] & 0xffffffffLL);
+            fu[rows[row].unit_start + t - rows[row].t0] = (int32_t)q;
+        }
+        for (auto& p : far) {
+            const int row = p.first / L.block, t = p.second / kTile;
+            const int q = fu[rows[row].unit_start + t - rows[row].t0];
+            fm[(size_t)q * L.block + (p.first - row * L.block)] |= 1ull << (p.second - t * kTile);
+        }
+        HIP_TRY(up(L.off_far_unit, fu.data(), fu.size() * 4));
+        if (!fm.empty()) HIP_TRY(up(L.off_far_mask, fm.data(), fm.size() * 8));
+    }
     // flat grid maps: (system, local block) of every workgroup
     {
         std::vector<int32_t> mf, mv, mb, ma;

@@ -18,7 +18,8 @@ namespace ff {
 
 constexpr int kAtomAlign = 512;      // single-system padding (largest I-block)
 constexpr int kTile = 64;            // j-tile: one atom per lane of a wavefront
-constexpr int kExclWindow = 64;      // exclusions reach at most 64 atoms ahead
+constexpr int kExclWindow = 64;      // exclusions of this reach live in a per-atom bitmask;
+                                     // farther ones in per-unit masks (far units)
 constexpr int kMaxM = 32;            // largest L-BFGS memory
 constexpr int kNumSlots = 8;         // point slots (x and grad) of the optimizer
 constexpr int kMaxTerms = 2 * kMaxM + 2;   // linear-combination terms of a direction
@@ -199,6 +200,7 @@ struct Layout {
     int32_t n_sys;
     int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;   // n, np: totals over the batch
     int32_t n_bonds, n_angles, n_dihedrals, n_terms_slots, n_bonded_blocks;
+    int32_t n_far_units;      // units holding an excluded pair more than kExclWindow apart
     int32_t n_fin_blocks;
     // flat grids: workgroup b of a pass handles (system, local block) = map[b]
     int32_t n_vec_blocks, n_acc_blocks;
@@ -215,6 +217,8 @@ struct Layout {
     size_t off_fb, off_eb, off_inc_start, off_inc;
     size_t off_red, off_vec;
     size_t off_map_fin, off_map_vec, off_map_bonded, off_map_acc;   // int2 maps of the flat grids
+    size_t off_far_unit;      // int32 per unit: its far-mask block, or -1
+    size_t off_far_mask;      // uint64 [n_far_units][block]: bit jl = pair (i, tile atom jl) excluded
     size_t total;
 };
 

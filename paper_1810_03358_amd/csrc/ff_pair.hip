@@ -237,10 +237,11 @@ __device__ __forceinline__ void close_pair32(const IAtoms32<IPL>& I, int k, floa
     }
 }
 
-template <int IPL, bool MASKED, bool CHECK>
+template <int IPL, bool MASKED, bool CHECK, bool FAR = false>
 __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const float2* __restrict__ s_c,
                                        const float4* __restrict__ s_lo, const float4* __restrict__ s_ilo,
                                        int lane, int il0, int i0, int J0, const uint64_t* __restrict__ EX,
+                                       const uint64_t* __restrict__ s_far,
                                        const IAtoms32<IPL>& I, float (&fx)[IPL], float (&fy)[IPL],
                                        float (&fz)[IPL], double (&gx)[IPL], double (&gy)[IPL],
                                        double (&gz)[IPL], float& fjx, float& fjy, float& fjz,
@@ -264,7 +265,10 @@ __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const fl
             if (MASKED) {
                 const int delta = J0 + (js & (kTile - 1)) - (i0 + k * 64);
                 const unsigned dm1 = (unsigned)(delta - 1);
-                const bool ex = dm1 < (unsigned)kExclWindow && ((excl[k] >> (dm1 & 63u)) & 1ull);
+                bool ex = dm1 < (unsigned)kExclWindow && ((excl[k] >> (dm1 & 63u)) & 1ull);
+                // far exclusions: this unit's mask of the i-atom, read from LDS
+                // every step (a register copy would raise the kernel's VGPRs)
+                if (FAR) ex = ex || ((s_far[il0 + k * 64] >> (js & (kTile - 1))) & 1ull);
                 r2 = (delta > 0 && !ex) ? r2 : __builtin_inff();
             }
             if (CHECK && r2 < kCorrR2)
@@ -320,7 +324,10 @@ __device__ __forceinline__ void block_energy_store(double e, double* out) {
     if (threadIdx.x == 0) *out = red[0];
 }
 
-template <int WAVES, int IPL>
+// HAS_FAR: the context has excluded pairs more than kExclWindow apart (the
+// kernel then checks every tile for a far-exclusion mask; the check costs a
+// few registers, so contexts without such pairs run the kernel without it).
+template <int WAVES, int IPL, bool HAS_FAR>
 __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
     const Layout& L = a.L;
     const int wg = blockIdx.x;
@@ -335,6 +342,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
     const float* C6 = at<float>(a.ws, L.off_c6);
     const float* Q = at<float>(a.ws, L.off_q);
     const uint64_t* EX = at<uint64_t>(a.ws, L.off_excl);
+    const int32_t* FU = at<int32_t>(a.ws, L.off_far_unit);
+    const uint64_t* FM = at<uint64_t>(a.ws, L.off_far_mask);
     const int I0 = ch.row * B;
 
     IAtoms32<IPL> I;
@@ -375,6 +384,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
     __shared__ float2 s_c[2 * kTile];
     __shared__ float4 s_lo[2 * kTile];
     __shared__ float s_fj[WAVES][3][kTile];
+    __shared__ uint64_t s_far[HAS_FAR ? B : 1];      // far-exclusion masks of a far unit
     double e64 = 0.0;
     const int t_masked_end = (I0 + B) / kTile + 1;   // tiles that can hold j <= i or exclusions
     for (int t = ch.t_begin; t < ch.t_end; ++t) {
@@ -410,14 +420,22 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
         const float gyb = fmaxf(0.0f, fmaxf(s_jbox[1] - ib[4], ib[1] - s_jbox[4]));
         const float gzb = fmaxf(0.0f, fmaxf(s_jbox[2] - ib[5], ib[2] - s_jbox[5]));
         const bool far = gxb * gxb + gyb * gyb + gzb * gzb >= kCorrR2;
-        if (t < t_masked_end)
-            tile32<IPL, true, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, I, fx, fy, fz, gx, gy, gz,
+        const int fu = HAS_FAR ? FU[ch.unit_base + t - ch.t_begin] : -1;
+        if (HAS_FAR && fu >= 0) {
+            // the unit holds excluded pairs more than kExclWindow apart: each
+            // lane copies the masks of its i-atoms (and only reads its own)
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) s_far[il0 + k * 64] = FM[(size_t)fu * B + il0 + k * 64];
+            tile32<IPL, true, true, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx,
+                                          gy, gz, fjx, fjy, fjz, e32, e64);
+        } else if (t < t_masked_end)
+            tile32<IPL, true, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx, gy, gz,
                                     fjx, fjy, fjz, e32, e64);
         else if (!far)
-            tile32<IPL, false, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, I, fx, fy, fz, gx, gy, gz,
+            tile32<IPL, false, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx, gy, gz,
                                      fjx, fjy, fjz, e32, e64);
         else
-            tile32<IPL, false, false>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, I, fx, fy, fz, gx, gy, gz,
+            tile32<IPL, false, false>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx, gy, gz,
                                       fjx, fjy, fjz, e32, e64);
 #pragma unroll
         for (int k = 0; k < IPL; ++k) { gx[k] += fx[k]; gy[k] += fy[k]; gz[k] += fz[k]; }
@@ -451,12 +469,12 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
 
 // ---------------------------------------------------------------- FP64 pairs
 
-template <int IPL, bool MASKED>
+template <int IPL, bool MASKED, bool FAR = false>
 __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const double2* __restrict__ s_c,
                                        int lane, int J0, const double (&xi)[IPL], const double (&yi)[IPL],
                                        const double (&zi)[IPL], const double (&c12i)[IPL],
                                        const double (&c6i)[IPL], const double (&qi)[IPL],
-                                       const uint64_t (&excl)[IPL], const int (&idx)[IPL],
+                                       const uint64_t (&excl)[IPL], const uint64_t (&fmask)[IPL], const int (&idx)[IPL],
                                        double (&gx)[IPL], double (&gy)[IPL], double (&gz)[IPL],
                                        double& fjx, double& fjy, double& fjz, double& e) {
 #pragma unroll 2
@@ -471,7 +489,8 @@ __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const d
             if (MASKED) {
                 const int delta = J0 + (js & (kTile - 1)) - idx[k];
                 const unsigned dm1 = (unsigned)(delta - 1);
-                const bool ex = dm1 < (unsigned)kExclWindow && ((excl[k] >> (dm1 & 63u)) & 1ull);
+                bool ex = dm1 < (unsigned)kExclWindow && ((excl[k] >> (dm1 & 63u)) & 1ull);
+                if (FAR) ex = ex || ((fmask[k] >> (js & (kTile - 1))) & 1ull);
                 r2 = (delta > 0 && !ex) ? r2 : __builtin_inf();
             }
             const double rinv = rsqrt(r2);
@@ -506,6 +525,9 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
     const double* C6 = at<double>(a.ws, L.off_c6d);
     const double* Q = at<double>(a.ws, L.off_qd);
     const uint64_t* EX = at<uint64_t>(a.ws, L.off_excl);
+    const int32_t* FU = at<int32_t>(a.ws, L.off_far_unit);
+    const uint64_t* FM = at<uint64_t>(a.ws, L.off_far_mask);
+    const uint64_t fnone[IPL] = {};
     const int I0 = ch.row * B;
 
     double xi[IPL], yi[IPL], zi[IPL], c12i[IPL], c6i[IPL], qi[IPL], gx[IPL], gy[IPL], gz[IPL];
@@ -541,10 +563,20 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
         }
         __syncthreads();
         double fjx = 0.0, fjy = 0.0, fjz = 0.0;
-        if (t < t_masked_end)
-            tile64<IPL, true>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, idx, gx, gy, gz, fjx, fjy, fjz, e);
-        else
-            tile64<IPL, false>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, idx, gx, gy, gz, fjx, fjy, fjz, e);
+        const int fu = FU[ch.unit_base + t - ch.t_begin];
+        if (fu >= 0) {
+            uint64_t fmask[IPL];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) fmask[k] = FM[(size_t)fu * B + wave * 64 * IPL + k * 64 + lane];
+            tile64<IPL, true, true>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, fmask, idx, gx, gy, gz,
+                                    fjx, fjy, fjz, e);
+        } else if (t < t_masked_end) {
+            tile64<IPL, true>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, fnone, idx, gx, gy, gz, fjx, fjy,
+                              fjz, e);
+        } else {
+            tile64<IPL, false>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, fnone, idx, gx, gy, gz, fjx,
+                               fjy, fjz, e);
+        }
         s_fj[wave][0][lane] = fjx;
         s_fj[wave][1][lane] = fjy;
         s_fj[wave][2][lane] = fjz;
@@ -585,7 +617,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
 #define FF_PAIR_CASE(ID)                                                                           \
     case ID: {                                                                                     \
         constexpr TileConfig T = kTileConfigs[ID];                                                 \
-        if (prec) hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
+        if (prec && a.L.n_far_units > 0)                                                              \
+            hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32, true>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
+        else if (prec)                                                                                \
+            hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32, false>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
         else hipLaunchKernelGGL((k_pair64<T.waves64, T.ipl64>), dim3(grid < kPair64Grid ? grid : kPair64Grid), \
                                 dim3(64 * T.waves64), 0, s, a);                                                 \
         break;                                                                                     \

@@ -58,3 +58,23 @@ def torsion_chain(n, seed):
     s["dihedrals"] = np.stack([np.arange(nd) + k for k in range(4)], axis=1).astype(np.int32)
     s["dihedral_v"] = rng.uniform(-2.0, 2.0, size=(nd, 4))
     return s
+
+
+def crosslinked_chain(n, seed):
+    """torsion_chain(n, seed) plus cross-link bonds, and the angles around
+    them, between atoms far apart in index: their 1-2 and 1-3 exclusions
+    reach well beyond 64 atoms (in diagonal and in off-diagonal pair tiles
+    for every block size)."""
+    s = torsion_chain(n, seed)
+    links = [(10, 100), (5, min(700, n - 100)), (n // 2, n - 50), (n - 200, n - 40)]
+    bonds = [tuple(b) for b in s["bonds"]] + links
+    angles = [tuple(a) for a in s["angles"]]
+    for i, j in links:
+        angles += [(i - 1, i, j), (i, j, j + 1)]
+    s["bonds"] = np.asarray(bonds, np.int32)
+    s["bond_k"] = np.concatenate([s["bond_k"], np.full(len(links), 300.0)])
+    s["bond_r0"] = np.concatenate([s["bond_r0"], np.full(len(links), 1.5)])
+    s["angles"] = np.asarray(angles, np.int32)
+    s["angle_k"] = np.concatenate([s["angle_k"], np.full(2 * len(links), 50.0)])
+    s["angle_t0"] = np.concatenate([s["angle_t0"], np.full(2 * len(links), math.radians(109.5))])
+    return s

@@ -74,12 +74,6 @@ def test_create_rejects_bad_input_before_touching_the_device():
     bad_bond["bonds"][3, 1] = 20
     assert _create_status(bad_bond) == ff.FF_ERR_ARG
     assert "out of range" in N.last_error()
-    far = dict(good, bonds=good["bonds"].copy())
-    far["bonds"][0] = (0, 19)
-    far_big = chain_system(100, 1)
-    far_big["bonds"] = far_big["bonds"].copy()
-    far_big["bonds"][0] = (0, 90)
-    assert _create_status(far_big) == ff.FF_ERR_UNSUPPORTED
     neg = dict(good, sigma=-good["sigma"])
     assert _create_status(neg) == ff.FF_ERR_ARG
     assert _create_status(good, ws_ptr=257) == ff.FF_ERR_WORKSPACE
@@ -158,3 +152,19 @@ def test_energy_profile_rejects_bad_arguments_on_the_host():
     out = (C.c_double * 2)()
     ctx = C.c_void_p(0)
     assert lib.ff_energy_profile(ctx, C.c_void_p(256), t, 2, out, 0, None) == ff.FF_ERR_ARG
+
+
+def test_far_exclusions_are_accepted_and_sized():
+    """Bonds between atoms more than 64 apart (cross-links, ring closures) get
+    per-unit exclusion masks: the workspace grows by one mask block per pair
+    unit that holds such a pair."""
+    from tests.systems import crosslinked_chain
+    plain = chain_system(1100, 5)
+    linked = crosslinked_chain(1100, 5)
+    lib = N.load()
+    a = (N.FFSystem * 1)(ff.HostSystem(plain).c)
+    b = (N.FFSystem * 1)(ff.HostSystem(linked).c)
+    for cfg, block in enumerate(t[0] for t in ff.tile_configs()):
+        wa = lib.ff_workspace_bytes_tiled(a, 1, 10, cfg, 2)
+        wb = lib.ff_workspace_bytes_tiled(b, 1, 10, cfg, 2)
+        assert wa > 0 and wb > wa

@@ -16,7 +16,7 @@ import torch
 import oracle
 import paper_1810_03358_amd as ff
 from synth import chain_system
-from tests.systems import torsion_chain
+from tests.systems import crosslinked_chain, torsion_chain
 from tests.test_gpu_energy import abs_pair_force_sum
 
 pytestmark = pytest.mark.gpu
@@ -70,3 +70,37 @@ def test_autotune_returns_a_working_tiling():
     for k, s in enumerate(systems):
         e_ref, _ = oracle.energy_grad(s, s["x"])
         assert abs(float(e.cpu()[k]) - e_ref) <= 1e-9 * abs(e_ref)
+
+
+@pytest.fixture(scope="module")
+def linked():
+    s = crosslinked_chain(1100, 5)
+    e, g = oracle.energy_grad(s, s["x"])
+    return s, e, g, abs_pair_force_sum(s, s["x"])
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_far_exclusions_match_the_oracle_for_every_tiling(linked, cfg):
+    s, e_ref, g_ref, pair_force_sum = linked
+    print(f"far exclusions cfg={cfg}", flush=True)
+    e, g = _run(s, s["x"], "fp64", (cfg, 2))
+    assert abs(e - e_ref) <= 1e-11 * abs(e_ref)
+    np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-11 * np.abs(g_ref).max())
+    e32, g32 = _run(s, s["x"], "fp32", (cfg, 2))
+    assert abs(e32 - e_ref) <= 1e-6 * abs(e_ref)
+    bound = 2.0 ** -16 * pair_force_sum[:, None] + 1e-9 * np.abs(g_ref).max()
+    assert np.all(np.abs(g32 - g_ref) <= bound), np.abs(g32 - g_ref).max()
+
+
+def test_far_exclusions_minimization_follows_the_oracle():
+    s = crosslinked_chain(600, 8)
+    sysc = oracle.System(s)
+    ref = oracle.minimize(lambda v: oracle.energy_grad(sysc, v.reshape(-1, 3)), s["x"].ravel(),
+                          oracle.MinParams(method=oracle.LBFGS, max_iter=20))
+    ctx = ff.Context(s, m_max=10)
+    x = torch.tensor(s["x"], dtype=torch.float64, device="cuda")
+    print("far exclusions minimize", flush=True)
+    r = ctx.minimize(x, "lbfgs", max_iter=20)
+    tr = ctx.trace()
+    assert r["iters"] == ref.iters == 20 and r["evals"] == ref.evals
+    np.testing.assert_allclose(tr[:20, 0], [t[0] for t in ref.trace], rtol=1e-9)
