@@ -134,16 +134,85 @@ def batch_bench(args):
     ctx.close()
 
 
+def learned_bench(args):
+    """The learned warm start against plain L-BFGS: held-out 10,000-atom
+    chains (seed 300000 + k; compacted start for even k, extended for odd k),
+    each minimized alone to |grad E|_inf < 1e-3 (FP32 pair sums) from its
+    stored start (plain) and from the learned start (features, network, a
+    200-iteration race of the start and two displaced candidates, then
+    L-BFGS from the winner), and, as a control, with the race's restart but
+    no network.  Per-system times include everything after the start point
+    is resident in HBM; the network was trained beforehand by
+    paper_1810_03358_amd.train_warmstart on other chains."""
+    import numpy as np
+    import torch
+    import paper_1810_03358_amd as ff
+    from paper_1810_03358_amd import learn as L
+    from paper_1810_03358_amd.train_warmstart import DEFAULT_WEIGHTS
+    from synth import chain_system
+
+    dev = torch.device("cuda:0")
+    path = args.weights or DEFAULT_WEIGHTS
+    net = L.Net.load(path, device=dev)
+    systems = [chain_system(args.test_atoms, 300_000 + k, compact=k % 2 == 0) for k in range(args.test_chains)]
+    rows = L.evaluate(net, systems, lambda s: ff.Context(s, device=dev), max_iter=args.learned_iters,
+                      control=not args.no_control, device=dev, log=lambda m: print(m, file=sys.stderr, flush=True))
+    pt = np.array([r["plain_time"] for r in rows])
+    lt = np.array([r["learned_time"] for r in rows])
+    both = np.array([r["plain_term"] == "converged" and r["learned_term"] == "converged" for r in rows])
+    pe = np.array([r["plain_energy"] for r in rows])
+    le = np.array([r["learned_energy"] for r in rows])
+    out = {
+        "metric": "time to |grad E|_inf<1e-3 per system, plain vs learned",
+        "value": float(lt.mean()),
+        "unit": "s/system",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"learned{args.test_chains}x{args.test_atoms}",
+                   "test_chains": args.test_chains, "atoms": args.test_atoms,
+                   "starts": "even k compacted, odd k extended, seeds 300000+k",
+                   "method": f"L-BFGS m=10, LS_PAR, FP32 pair sums, tol 1e-3, max_iter {args.learned_iters}",
+                   "warm_start": "16-NN + centroid features, 3-layer BF16 MLP, race of x0, x0+0.5d, x0+d "
+                                 "over 200 iterations", "weights": os.path.relpath(path, ROOT)},
+        "plain_s_per_system": float(pt.mean()),
+        "learned_over_plain": float(lt.sum() / pt.sum()),
+        "median_time_ratio": float(np.median(lt / pt)),
+        "converged_plain": int(sum(r["plain_term"] == "converged" for r in rows)),
+        "converged_learned": int(sum(r["learned_term"] == "converged" for r in rows)),
+        "both_converged_time_ratio": float(lt[both].sum() / pt[both].sum()) if both.any() else None,
+        "learned_energy_lower": int(np.sum(le < pe)),
+        "energy_equal_1e-4": int(np.sum(np.abs(le - pe) <= 1e-4 * np.abs(pe))),
+        "mean_rel_energy_change": float(np.mean((le - pe) / np.abs(pe))),
+        "race_winner_counts": {str(k): int(sum(r["scale_taken"] == k for r in rows)) for k in (0.0, 0.5, 1.0)},
+    }
+    if not args.no_control:
+        ct = np.array([r["control_time"] for r in rows])
+        out["restart_control_s_per_system"] = float(ct.mean())
+        out["learned_over_restart_control"] = float(lt.sum() / ct.sum())
+    out["systems"] = [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()
+                       if k != "probe_energies"} for r in rows]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="chain50k", choices=["chain512", "chain10k", "chain50k", "batch256"])
+    ap.add_argument("--workload", default="chain50k",
+                    choices=["chain512", "chain10k", "chain50k", "batch256", "learned"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=2000, help="batch256: iteration limit per system")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--test-chains", type=int, default=8, help="learned: held-out chains")
+    ap.add_argument("--test-atoms", type=int, default=10_000, help="learned: atoms per held-out chain")
+    ap.add_argument("--learned-iters", type=int, default=60_000, help="learned: iteration limit per run")
+    ap.add_argument("--weights", default=None, help="learned: network file (default: the shipped one)")
+    ap.add_argument("--no-control", action="store_true", help="learned: skip the restart-only control")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -154,6 +223,9 @@ def main():
 
     if args.workload == "batch256":
         batch_bench(args)
+        return
+    if args.workload == "learned":
+        learned_bench(args)
         return
 
     import torch

@@ -12,7 +12,11 @@ shares no code with the HIP path.
   eq. 4), FGM (Algorithm 1), CG (Algorithm 2, Polak-Ribiere-Polyak beta of
   section 4) and L-BFGS (Algorithms 3 and 4), heavy ball (eq. HB) and the
   optimized gradient method (eq. optim), in the paper's order and notation.
+* ``learn`` (numpy): the learned warm start, which is not in the paper: BF16
+  rounding, 16-nearest-neighbour features, the 3-layer network, its loss
+  gradient and Adam, by their definitions.
 """
+from . import learn  # noqa: F401
 from .energy import (System, energy_grad, energy_terms, atom_gradients, num_threads, build,  # noqa: F401
                      energy_profile)
 from .minimize import (  # noqa: F401

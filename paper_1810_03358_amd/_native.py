@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/ff.h (libff_mi355x.so)."""
+"""ctypes declarations of the C ABI in include/ff.h and include/ff_learn.h
+(libff_mi355x.so)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -50,6 +51,11 @@ EXPORTS = ("ff_workspace_bytes", "ff_workspace_bytes_batch", "ff_create", "ff_cr
            "ff_destroy", "ff_energy_grad", "ff_minimize", "ff_get_trace", "ff_time_pair", "ff_default_params",
            "ff_last_error", "ff_num_tile_configs", "ff_tile_config_info", "ff_workspace_bytes_tiled",
            "ff_create_tiled", "ff_get_tiling", "ff_autotune_workspace_bytes", "ff_autotune", "ff_energy_profile")
+
+LEARN_EXPORTS = ("ff_learn_param_count", "ff_learn_workspace_bytes", "ff_learn_last_error", "ff_learn_features",
+                 "ff_learn_gemm", "ff_learn_forward", "ff_learn_backward", "ff_learn_adam", "ff_learn_to_bf16",
+                 "ff_learn_delta", "ff_learn_gather_rows", "ff_learn_displace", "ff_learn_select")
+FF_LEARN_NEIGHBORS, FF_LEARN_FEATURES, FF_LEARN_HIDDEN, FF_LEARN_OUT_PAD = 16, 128, 128, 16
 
 _lib = None
 
@@ -108,9 +114,32 @@ def load():
     lib.ff_energy_profile.restype = C.c_int
     lib.ff_last_error.argtypes = []
     lib.ff_last_error.restype = C.c_char_p
+    v, i32, i64, sz, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_float, C.c_double
+    lib.ff_learn_param_count.argtypes = []
+    lib.ff_learn_param_count.restype = i32
+    lib.ff_learn_workspace_bytes.argtypes = [i32]
+    lib.ff_learn_workspace_bytes.restype = sz
+    lib.ff_learn_last_error.argtypes = []
+    lib.ff_learn_last_error.restype = C.c_char_p
+    lib.ff_learn_features.argtypes = [i32, i32, v, v, v, v, v, v, v, v, v]
+    lib.ff_learn_gemm.argtypes = [i32, i32, i32, v, i64, i64, v, i64, i64, v, i32, v, i64, v, i64, v]
+    lib.ff_learn_forward.argtypes = [v, v, v, i32, v, sz, v, v]
+    lib.ff_learn_backward.argtypes = [v, v, v, i32, v, sz, v, v, v, v]
+    lib.ff_learn_adam.argtypes = [v, v, v, v, v, i32, f32, f32, f32, f32, v]
+    lib.ff_learn_to_bf16.argtypes = [v, i64, v, v]
+    lib.ff_learn_delta.argtypes = [v, v, i32, v, v]
+    lib.ff_learn_gather_rows.argtypes = [v, v, i32, i32, v, v]
+    lib.ff_learn_displace.argtypes = [v, v, i32, f64, v, v]
+    lib.ff_learn_select.argtypes = [i32, i32, v, v, v, v, v, v, v, v, v]
+    for name in LEARN_EXPORTS[3:]:
+        getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
 
 
 def last_error() -> str:
     return load().ff_last_error().decode()
+
+
+def learn_last_error() -> str:
+    return load().ff_learn_last_error().decode()

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["ff_pair.hip", "ff_optim.hip", "ff_api.hip"]
+SOURCES = ["ff_pair.hip", "ff_optim.hip", "ff_api.hip", "ff_learn.hip"]
 LIB = os.path.join(HERE, "libff_mi355x.so")
 
 # Packed FP32 instructions are switched off for every HIP translation unit.

@@ -414,7 +414,6 @@ __global__ void __launch_bounds__(kFinBlock) k_accept(Args a) {
     // acc_rows is fixed while this pass runs (the reduce kernel changes
     // hist_n afterwards)
     const int rows = c->acc_rows;
-    const int nh = method == M_LBFGS ? rows - 1 : 0;
     const bool active = row < rows;
     double* red = at<double>(a.ws, a.L.off_red) + si.red0;
     const int nbx = si.acc_bx;

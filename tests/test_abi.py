@@ -11,17 +11,22 @@ from paper_1810_03358_amd import _native as N
 from synth import chain_system
 from tests.systems import make_system
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ff.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ff_[a-z_]+)\s*\(", text)))
+def declared_functions(header=None):
+    names = [header] if header else sorted(f for f in os.listdir(INCLUDE) if f.endswith(".h"))
+    found = set()
+    for h in names:
+        text = open(os.path.join(INCLUDE, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        found |= set(re.findall(r"\b(ff_[a-z0-9_]+)\s*\(", text))
+    return sorted(found)
 
 
 def test_header_and_binding_agree():
-    assert declared_functions() == sorted(N.EXPORTS)
+    assert declared_functions("ff.h") == sorted(N.EXPORTS)
+    assert declared_functions("ff_learn.h") == sorted(N.LEARN_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
@@ -168,3 +173,28 @@ def test_far_exclusions_are_accepted_and_sized():
         wa = lib.ff_workspace_bytes_tiled(a, 1, 10, cfg, 2)
         wb = lib.ff_workspace_bytes_tiled(b, 1, 10, cfg, 2)
         assert wa > 0 and wb > wa
+
+
+def test_learn_entry_points_reject_bad_arguments_on_the_host():
+    lib = N.load()
+    assert lib.ff_learn_param_count() == 128 * 128 * 2 + 128 * 16 + 128 * 2 + 16
+    assert lib.ff_learn_workspace_bytes(0) == 0
+    assert lib.ff_learn_workspace_bytes(100) > 100 * 128 * 12
+    nul = None
+    p = C.c_void_p(256)
+    assert lib.ff_learn_features(0, 10, p, p, p, p, p, p, p, nul, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_features(1, 10, p, nul, p, p, p, p, p, nul, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_gemm(0, 1, 1, p, 1, 1, p, 1, 1, nul, 0, p, 1, nul, 1, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_gemm(1, 1, 1, p, 1, 1, p, 1, 1, nul, 0, nul, 1, nul, 1, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_forward(p, p, p, 10, p, 16, p, nul) == ff.FF_ERR_WORKSPACE
+    assert lib.ff_learn_forward(p, p, p, 10, C.c_void_p(257), 1 << 30, p, nul) == ff.FF_ERR_WORKSPACE
+    ws1 = lib.ff_learn_workspace_bytes(10)
+    assert lib.ff_learn_backward(p, p, p, 10, p, ws1, p, p, p, nul) == ff.FF_ERR_WORKSPACE
+    assert "workspace" in N.learn_last_error()
+    assert lib.ff_learn_adam(p, nul, p, p, p, 0, 1e-3, 0.9, 0.999, 1e-8, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_adam(p, nul, p, p, p, 1, 0.0, 0.9, 0.999, 1e-8, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_gather_rows(p, p, 5, 6, p, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_displace(p, p, 5, float("inf"), p, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_select(1, 0, p, p, p, p, p, p, nul, nul, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_to_bf16(p, 0, p, nul) == ff.FF_ERR_ARG
+    assert lib.ff_learn_delta(p, nul, 4, p, nul) == ff.FF_ERR_ARG
