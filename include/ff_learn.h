@@ -42,8 +42,10 @@ extern "C" {
  * (128*128 + 128 + 128*128 + 128 + 128*16 + 16 = 35 088). */
 int32_t ff_learn_param_count(void);
 
-/* Device workspace for ff_learn_forward with n_rows rows; ff_learn_backward
- * needs twice as much.  0 for n_rows < 1. */
+/* Device workspace for ff_learn_forward and ff_learn_backward with up to
+ * n_rows rows (the forward pass uses its first part: the activations; the
+ * backward pass also holds their gradients and 4 MiB of per-slice partial
+ * sums for the weight gradients).  0 for n_rows < 1. */
 size_t ff_learn_workspace_bytes(int32_t n_rows);
 
 /* Description of the last error of an ff_learn_* call on this thread. */
@@ -94,8 +96,9 @@ ff_status ff_learn_forward(const float *params, const uint16_t *params_bf16, con
  * (FP32, packed like params, device) is overwritten with d loss / d params,
  * computed from BF16 copies of the forward activations and of the output
  * and hidden-layer gradients, FP32 accumulation; bias gradients are FP32
- * column sums.  loss: one FP32 on the device.  workspace: 2 x
- * ff_learn_workspace_bytes(n_rows). */
+ * column sums; the weight gradients sum their k slices in a fixed order.
+ * loss: one FP32 on the device.  workspace: device, 256-byte aligned, at
+ * least ff_learn_workspace_bytes(n_rows). */
 ff_status ff_learn_backward(const float *params, const uint16_t *params_bf16, const uint16_t *features,
                             int32_t n_rows, void *workspace, size_t workspace_bytes, const float *target,
                             float *grad, float *loss, void *stream);

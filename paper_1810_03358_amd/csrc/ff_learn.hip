@@ -6,6 +6,7 @@
 // judge: ff_minimize starts from the displaced point only if that lowers E.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -109,28 +110,34 @@ __global__ void k_features(const double* __restrict__ xyz, const double* __restr
 // 4*(l/16)+q of its A / B fragment, rows 4*(l/16)+q of column l%16 of D).
 // Epilogue: + bias[n] (FP32, optional), ReLU (optional), FP32 result to C
 // (optional) and its BF16 rounding to Cb (optional).  One wavefront per
-// 16x16 tile of C; out-of-range rows, columns and k read as zero.
+// 16x16 tile of C and per slice [y*kc, (y+1)*kc) of k (blockIdx.y = y);
+// out-of-range rows, columns and k read as zero.  With several slices
+// (P != null) each wave stores its raw FP32 sums to P[y][m][n] and
+// k_splitk_reduce adds the slices in order and applies the epilogue, so the
+// result does not depend on timing.
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) k_gemm(int m, int n, int kdim, const uint16_t* __restrict__ A, long sa0,
-                                              long sa1, const uint16_t* __restrict__ B, long sb0, long sb1,
-                                              const float* __restrict__ bias, int relu, float* __restrict__ C,
-                                              long ldc, uint16_t* __restrict__ Cb, long ldcb) {
+__global__ void __launch_bounds__(256) k_gemm(int m, int n, int kdim, int kc, const uint16_t* __restrict__ A,
+                                              long sa0, long sa1, const uint16_t* __restrict__ B, long sb0,
+                                              long sb1, const float* __restrict__ bias, int relu,
+                                              float* __restrict__ C, long ldc, uint16_t* __restrict__ Cb,
+                                              long ldcb, float* __restrict__ P) {
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int tiles_n = (n + 15) / 16;
     const long tile = (long)blockIdx.x * 4 + wave;
     const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
     if ((long)tm * 16 >= m) return;
     const int row = tm * 16 + (l & 15), col = tn * 16 + (l & 15), kq = 4 * (l >> 4);
+    const int k_lo = blockIdx.y * kc, k_hi = min(kdim, k_lo + kc);
     f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < kdim; k0 += 16) {
+    for (int k0 = k_lo; k0 < k_hi; k0 += 16) {
         bf16x4_t av, bv;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = k0 + kq + q;
-            av[q] = (row < m && k < kdim) ? (short)A[row * sa0 + k * sa1] : (short)0;
-            bv[q] = (col < n && k < kdim) ? (short)B[k * sb0 + col * sb1] : (short)0;
+            av[q] = (row < m && k < k_hi) ? (short)A[row * sa0 + k * sa1] : (short)0;
+            bv[q] = (col < n && k < k_hi) ? (short)B[k * sb0 + col * sb1] : (short)0;
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
@@ -139,6 +146,10 @@ __global__ void __launch_bounds__(256) k_gemm(int m, int n, int kdim, const uint
         const int r = tm * 16 + kq + q;
         if (r >= m || col >= n) continue;
         float v = acc[q];
+        if (P) {
+            P[((long)blockIdx.y * m + r) * n + col] = v;
+            continue;
+        }
         if (bias) v += bias[col];
         if (relu) v = fmaxf(v, 0.0f);
         if (C) C[r * ldc + col] = v;
@@ -146,12 +157,45 @@ __global__ void __launch_bounds__(256) k_gemm(int m, int n, int kdim, const uint
     }
 }
 
+__global__ void k_splitk_reduce(int m, int n, int slices, const float* __restrict__ P,
+                                const float* __restrict__ bias, int relu, float* __restrict__ C, long ldc,
+                                uint16_t* __restrict__ Cb, long ldcb) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)m * n) return;
+    const int r = (int)(e / n), col = (int)(e - (long)r * n);
+    float v = 0.0f;
+    for (int y = 0; y < slices; ++y) v += P[(long)y * m * n + e];
+    if (bias) v += bias[col];
+    if (relu) v = fmaxf(v, 0.0f);
+    if (C) C[r * ldc + col] = v;
+    if (Cb) Cb[r * ldcb + col] = to_bf16(v);
+}
+
+// Scratch for the k slices of a product with few output tiles and a long k
+// (the weight gradients): at most kMaxSlices slices of a 128 x 128 result.
+constexpr int kMaxSlices = 64;
+constexpr long kSplitFloats = (long)kMaxSlices * FF_LEARN_HIDDEN * FF_LEARN_HIDDEN;
+
 hipError_t launch_gemm(int m, int n, int k, const uint16_t* A, long sa0, long sa1, const uint16_t* B, long sb0,
                        long sb1, const float* bias, int relu, float* C, long ldc, uint16_t* Cb, long ldcb,
-                       hipStream_t s) {
+                       hipStream_t s, float* split = nullptr, long split_floats = 0) {
     const long tiles = (long)((m + 15) / 16) * ((n + 15) / 16);
-    hipLaunchKernelGGL(k_gemm, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, m, n, k, A, sa0, sa1, B, sb0,
-                       sb1, bias, relu, C, ldc, Cb, ldcb);
+    int slices = 1;
+    // split k when the tiles alone cannot fill the chip: slices of >= 256
+    if (split && tiles < 1024 && k >= 512) {
+        const long by_k = k / 256, by_ws = split_floats / ((long)m * n);
+        slices = (int)std::max(1L, std::min({by_k, by_ws, (long)kMaxSlices}));
+    }
+    const int kc = slices == 1 ? k : ((k + slices - 1) / slices + 15) / 16 * 16;
+    slices = (k + kc - 1) / kc;
+    float* P = slices > 1 ? split : nullptr;
+    hipLaunchKernelGGL(k_gemm, dim3((unsigned)((tiles + 3) / 4), (unsigned)slices), dim3(256), 0, s, m, n, k, kc, A,
+                       sa0, sa1, B, sb0, sb1, bias, relu, C, ldc, Cb, ldcb, P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !P) return e;
+    const long mn = (long)m * n;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, m, n, slices, P, bias,
+                       relu, C, ldc, Cb, ldcb);
     return hipGetLastError();
 }
 
@@ -329,7 +373,11 @@ extern "C" {
 
 int32_t ff_learn_param_count(void) { return (int32_t)kParams; }
 
-size_t ff_learn_workspace_bytes(int32_t n_rows) { return n_rows < 1 ? 0 : act_bytes(n_rows) + 2 * 256; }
+// forward: the activations; backward: activations, their gradients and the
+// k-slice scratch of the weight gradients
+size_t backward_bytes(long n) { return 2 * act_bytes(n) + (size_t)kSplitFloats * 4; }
+
+size_t ff_learn_workspace_bytes(int32_t n_rows) { return n_rows < 1 ? 0 : backward_bytes(n_rows) + 2 * 256; }
 
 const char* ff_learn_last_error(void) { return g_learn_err.c_str(); }
 
@@ -377,7 +425,7 @@ ff_status ff_learn_backward(const float* params, const uint16_t* params_bf16, co
     g_learn_err.clear();
     if (!params || !params_bf16 || !features || n_rows < 1 || !workspace || !target || !grad || !loss)
         return lfail(FF_ERR_ARG, "null argument or no rows");
-    const size_t need = act_bytes(n_rows) * 2;
+    const size_t need = backward_bytes(n_rows);
     if (workspace_bytes < need || ((uintptr_t)workspace & 255))
         return lfail(FF_ERR_WORKSPACE, "workspace too small or misaligned (%zu needed)", need);
     hipStream_t st = (hipStream_t)stream;
@@ -387,6 +435,7 @@ ff_status ff_learn_backward(const float* params, const uint16_t* params_bf16, co
     // activations into the second half
     const Act t = carve(workspace, n);
     const Act d = carve((char*)workspace + act_bytes(n), n);
+    float* split = (float*)((char*)workspace + 2 * act_bytes(n));
     L_TRY(launch_gemm(n_rows, H, F, features, F, 1, params_bf16 + kW1, H, 1, params + kB1, 1, t.h1, H, t.h1b, H, st));
     L_TRY(launch_gemm(n_rows, H, H, t.h1b, H, 1, params_bf16 + kW2, H, 1, params + kB2, 1, t.h2, H, t.h2b, H, st));
     L_TRY(launch_gemm(n_rows, O, H, t.h2b, H, 1, params_bf16 + kW3, O, 1, params + kB3, 0, t.y, O, nullptr, 0, st));
@@ -398,21 +447,24 @@ ff_status ff_learn_backward(const float* params, const uint16_t* params_bf16, co
     hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, n_rows, 1, row_loss, 1.0 / (3.0 * n), loss);
     L_TRY(hipGetLastError());
     // layer 3: dW3 = H2^T dY, db3 = colsum dY, dH2 = dY W3^T (masked by H2 > 0)
-    L_TRY(launch_gemm(H, O, n_rows, t.h2b, 1, H, dyb, O, 1, nullptr, 0, grad + kW3, O, nullptr, 0, st));
+    L_TRY(launch_gemm(H, O, n_rows, t.h2b, 1, H, dyb, O, 1, nullptr, 0, grad + kW3, O, nullptr, 0, st, split,
+                      kSplitFloats));
     hipLaunchKernelGGL(k_colsum, dim3(O), dim3(256), 0, st, n_rows, (int)O, d.y, 1.0, grad + kB3);
     L_TRY(hipGetLastError());
     L_TRY(launch_gemm(n_rows, H, O, dyb, O, 1, params_bf16 + kW3, 1, O, nullptr, 0, d.h2, H, nullptr, 0, st));
     hipLaunchKernelGGL(k_relu_back, dim3((unsigned)((n * H + 255) / 256)), dim3(256), 0, st, n * H, t.h2, d.h2, d.h2b);
     L_TRY(hipGetLastError());
     // layer 2: dW2 = H1^T dH2, db2, dH1 = dH2 W2^T (masked by H1 > 0)
-    L_TRY(launch_gemm(H, H, n_rows, t.h1b, 1, H, d.h2b, H, 1, nullptr, 0, grad + kW2, H, nullptr, 0, st));
+    L_TRY(launch_gemm(H, H, n_rows, t.h1b, 1, H, d.h2b, H, 1, nullptr, 0, grad + kW2, H, nullptr, 0, st, split,
+                      kSplitFloats));
     hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, n_rows, (int)H, d.h2, 1.0, grad + kB2);
     L_TRY(hipGetLastError());
     L_TRY(launch_gemm(n_rows, H, H, d.h2b, H, 1, params_bf16 + kW2, 1, H, nullptr, 0, d.h1, H, nullptr, 0, st));
     hipLaunchKernelGGL(k_relu_back, dim3((unsigned)((n * H + 255) / 256)), dim3(256), 0, st, n * H, t.h1, d.h1, d.h1b);
     L_TRY(hipGetLastError());
     // layer 1: dW1 = X^T dH1, db1
-    L_TRY(launch_gemm(F, H, n_rows, features, 1, F, d.h1b, H, 1, nullptr, 0, grad + kW1, H, nullptr, 0, st));
+    L_TRY(launch_gemm(F, H, n_rows, features, 1, F, d.h1b, H, 1, nullptr, 0, grad + kW1, H, nullptr, 0, st, split,
+                      kSplitFloats));
     hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, n_rows, (int)H, d.h1, 1.0, grad + kB1);
     L_TRY(hipGetLastError());
     return FF_OK;

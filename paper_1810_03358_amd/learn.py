@@ -117,7 +117,7 @@ class Net:
         self._ws = None
 
     def _workspace(self, rows: int, backward: bool) -> tuple[torch.Tensor, int, int]:
-        need = int(N.load().ff_learn_workspace_bytes(rows)) * (2 if backward else 1)
+        need = int(N.load().ff_learn_workspace_bytes(rows))
         if self._ws is None or self._ws.numel() < need + 256:
             self._ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()

@@ -189,7 +189,7 @@ def test_learn_entry_points_reject_bad_arguments_on_the_host():
     assert lib.ff_learn_forward(p, p, p, 10, p, 16, p, nul) == ff.FF_ERR_WORKSPACE
     assert lib.ff_learn_forward(p, p, p, 10, C.c_void_p(257), 1 << 30, p, nul) == ff.FF_ERR_WORKSPACE
     ws1 = lib.ff_learn_workspace_bytes(10)
-    assert lib.ff_learn_backward(p, p, p, 10, p, ws1, p, p, p, nul) == ff.FF_ERR_WORKSPACE
+    assert lib.ff_learn_backward(p, p, p, 10, p, ws1 - 1024, p, p, p, nul) == ff.FF_ERR_WORKSPACE
     assert "workspace" in N.learn_last_error()
     assert lib.ff_learn_adam(p, nul, p, p, p, 0, 1e-3, 0.9, 0.999, 1e-8, nul) == ff.FF_ERR_ARG
     assert lib.ff_learn_adam(p, nul, p, p, p, 1, 0.0, 0.9, 0.999, 1e-8, nul) == ff.FF_ERR_ARG
