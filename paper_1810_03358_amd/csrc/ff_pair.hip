@@ -605,9 +605,17 @@ constexpr int kPair64Grid = 4096;
 
 template <int WAVES, int IPL>
 __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
-    // one system: a single activity check for the whole launch; a batch
-    // checks the system of every chunk
-    if (a.L.n_sys == 1 && !eval_active(a, 0, 0)) return;
+    // one activity check for the whole launch: a single system's, or, for a
+    // batch, whether any system evaluates in FP64 this cycle (the threads
+    // read the control blocks side by side); then each chunk checks its own
+    // system
+    if (a.L.n_sys == 1) {
+        if (!eval_active(a, 0, 0)) return;
+    } else if (!a.direct) {
+        int any = 0;
+        for (int s = threadIdx.x; s < a.L.n_sys && !any; s += blockDim.x) any = eval_active(a, s, 0) ? 1 : 0;
+        if (!__syncthreads_or(any)) return;
+    }
     for (int wg = blockIdx.x; wg < a.L.n_chunks; wg += gridDim.x) pair64_chunk<WAVES, IPL>(a, wg);
 }
 

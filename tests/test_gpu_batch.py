@@ -97,3 +97,23 @@ def test_batch_fp32_certified_results():
         assert res[k]["energy"] == pytest.approx(e_ref, rel=1e-9), k
         assert res[k]["grad_inf"] == pytest.approx(np.abs(g_ref).max(), rel=1e-6), k
         assert res[k]["energy"] < 0
+
+
+def test_batch_mixed_precision_cycles():
+    """In FP32 mode a small system reaches its FP64 end game while a chain of
+    the same batch is still evaluated in FP32: cycles then run both pair
+    kernels, each on its own systems."""
+    sig, eps = 3.3, 0.2
+    lj = make_system([[0, 0, 0], [1.5 * sig, 0.0, 0.0]], sigma=[sig, sig], eps=[eps, eps])
+    chain = chain_system(400, 61)
+    systems = [chain, lj]
+    ctx = ff.Context(systems, m_max=10)
+    x = concat(systems)
+    res = ctx.minimize(x, "lbfgs", tol=1e-8, max_iter=100, precision="fp32")
+    assert res[1]["term"] == ff.FF_CONVERGED and res[1]["evals_fp64"] >= 1
+    assert res[1]["energy"] == pytest.approx(-eps, rel=1e-10)
+    assert res[0]["term"] == ff.FF_MAX_ITER
+    xs = x.cpu().numpy()
+    e_ref, g_ref = oracle.energy_grad(chain, xs[:400])
+    assert res[0]["energy"] == pytest.approx(e_ref, rel=1e-9)
+    assert res[0]["grad_inf"] == pytest.approx(np.abs(g_ref).max(), rel=1e-6)
