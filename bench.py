@@ -139,9 +139,10 @@ def learned_bench(args):
     chains (seed 300000 + k; compacted start for even k, extended for odd k),
     each minimized alone to |grad E|_inf < 1e-3 (FP32 pair sums) from its
     stored start (plain) and from the learned start (features, network, a
-    200-iteration race of the start and two displaced candidates, then
-    L-BFGS from the winner), and, as a control, with the race's restart but
-    no network.  Per-system times include everything after the start point
+    race of the start and two displaced candidates over 200-1000 iterations,
+    then L-BFGS from the winner), and, as controls, with the race's restart
+    but no network and with the network's displacements in random
+    directions.  Per-system times include everything after the start point
     is resident in HBM; the network was trained beforehand by
     paper_1810_03358_amd.train_warmstart on other chains."""
     import numpy as np
@@ -154,9 +155,12 @@ def learned_bench(args):
     dev = torch.device("cuda:0")
     path = args.weights or DEFAULT_WEIGHTS
     net = L.Net.load(path, device=dev)
-    systems = [chain_system(args.test_atoms, 300_000 + k, compact=k % 2 == 0) for k in range(args.test_chains)]
+    ks = range(args.test_offset, args.test_offset + args.test_chains)
+    systems = [chain_system(args.test_atoms, 300_000 + k, compact=k % 2 == 0) for k in ks]
     rows = L.evaluate(net, systems, lambda s: ff.Context(s, device=dev), max_iter=args.learned_iters,
-                      control=not args.no_control, device=dev, log=lambda m: print(m, file=sys.stderr, flush=True))
+                      probe_iters=args.probe_iters, control=not args.no_control,
+                      random_control=args.random_control, device=dev,
+                      log=lambda m: print(m, file=sys.stderr, flush=True))
     pt = np.array([r["plain_time"] for r in rows])
     lt = np.array([r["learned_time"] for r in rows])
     both = np.array([r["plain_term"] == "converged" and r["learned_term"] == "converged" for r in rows])
@@ -172,11 +176,12 @@ def learned_bench(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"learned{args.test_chains}x{args.test_atoms}",
-                   "test_chains": args.test_chains, "atoms": args.test_atoms,
+                   "test_chains": args.test_chains, "first_chain": args.test_offset, "atoms": args.test_atoms,
                    "starts": "even k compacted, odd k extended, seeds 300000+k",
                    "method": f"L-BFGS m=10, LS_PAR, FP32 pair sums, tol 1e-3, max_iter {args.learned_iters}",
                    "warm_start": "16-NN + centroid features, 3-layer BF16 MLP, race of x0, x0+0.5d, x0+d "
-                                 "over 200 iterations", "weights": os.path.relpath(path, ROOT)},
+                                 "over " + (f"{args.probe_iters}" if args.probe_iters else "min(1000, max(200, n/10))")
+                                 + " iterations", "weights": os.path.relpath(path, ROOT)},
         "plain_s_per_system": float(pt.mean()),
         "learned_over_plain": float(lt.sum() / pt.sum()),
         "median_time_ratio": float(np.median(lt / pt)),
@@ -188,12 +193,17 @@ def learned_bench(args):
         "mean_rel_energy_change": float(np.mean((le - pe) / np.abs(pe))),
         "race_winner_counts": {str(k): int(sum(r["scale_taken"] == k for r in rows)) for k in (0.0, 0.5, 1.0)},
     }
+    if args.random_control:
+        rt = np.array([r["random_time"] for r in rows])
+        out["random_direction_control_s_per_system"] = float(rt.mean())
+        out["learned_over_random_control"] = float(lt.sum() / rt.sum())
     if not args.no_control:
         ct = np.array([r["control_time"] for r in rows])
         out["restart_control_s_per_system"] = float(ct.mean())
         out["learned_over_restart_control"] = float(lt.sum() / ct.sum())
-    out["systems"] = [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()
-                       if k != "probe_energies"} for r in rows]
+    out["systems"] = [{k: (round(v, 6) if isinstance(v, float) else
+                           [float(f"{e:.6e}") for e in v] if k == "probe_energies" else v) for k, v in r.items()}
+                      for r in rows]
     print(json.dumps(out), flush=True)
 
 
@@ -209,10 +219,15 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=2000, help="batch256: iteration limit per system")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--test-chains", type=int, default=8, help="learned: held-out chains")
+    ap.add_argument("--test-offset", type=int, default=0, help="learned: index of the first held-out chain")
     ap.add_argument("--test-atoms", type=int, default=10_000, help="learned: atoms per held-out chain")
     ap.add_argument("--learned-iters", type=int, default=60_000, help="learned: iteration limit per run")
     ap.add_argument("--weights", default=None, help="learned: network file (default: the shipped one)")
     ap.add_argument("--no-control", action="store_true", help="learned: skip the restart-only control")
+    ap.add_argument("--probe-iters", type=int, default=None,
+                    help="learned: length of the race (default: by system size, 200 to 1000)")
+    ap.add_argument("--random-control", action="store_true",
+                    help="learned: add the race with the displacements in random directions")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()

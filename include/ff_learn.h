@@ -6,7 +6,8 @@
  * clashing poses (sections 3 and 5.3); this part learns, from (start,
  * minimum) pairs that ff_minimize itself produces, a per-atom displacement
  * that is applied to a start before L-BFGS.  The minimizer stays the judge:
- * ff_learn_select keeps a displaced start only where it lowers the energy.
+ * a displaced start is kept per system only where the energy prefers it
+ * (ff_learn_select compares two points of every system).
  *
  * The network is a 3-layer perceptron on per-atom features:
  *   H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), Y = H2 W3 + b3,

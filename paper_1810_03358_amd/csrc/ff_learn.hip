@@ -2,8 +2,8 @@
 // nearest atoms of the same system, a 3-layer perceptron (BF16 weights and
 // activations, FP32 accumulation on the matrix cores) that predicts a
 // displacement of every atom, its training kernels, and the application of
-// the displacement before a minimization.  The minimizer itself stays the
-// judge: ff_minimize starts from the displaced point only if that lowers E.
+// the displacement before a minimization.  The minimizer stays the judge: a
+// displaced start is kept per system only where the energy prefers it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,7 +24,6 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------- features
 // One thread per atom: the 16 nearest other atoms of its system by FP64

@@ -310,7 +310,7 @@ def _sync_time(fn):
 
 
 def probe_start(probe_ctx, sa: SystemArrays, net: Net, x: torch.Tensor, scales=(0.5, 1.0), probe_iters: int = 200,
-                tol: float = 1e-3, precision="fp32", stream=None):
+                tol: float = 1e-3, precision="fp32", transform=None, stream=None):
     """Learned start of one system, chosen by a short race: x and
     x + s * network(features(x)) for each s in `scales` are minimized side by
     side (probe_ctx: a batch context holding
@@ -319,13 +319,16 @@ def probe_start(probe_ctx, sa: SystemArrays, net: Net, x: torch.Tensor, scales=(
     winner (0: x itself), per-candidate results).  The start energy is no
     guide here: a displaced start that brings the atoms most of the way to
     the minimum usually has a new clash, so its energy is higher until the
-    first iterations have relieved it."""
+    first iterations have relieved it.  `transform(y)`, if given, replaces
+    the network's output before it is applied (the evaluation's controls)."""
     n3 = x.numel()
     k = 1 + len(scales)
     if probe_ctx.n_sys != k or probe_ctx.n * 3 != k * n3:
         raise ValueError("probe context must hold 1 + len(scales) copies of the system")
     f = features(sa, x, stream=stream)
     y = net.forward(f, stream=stream)
+    if transform is not None:
+        y = transform(y)
     xb = torch.empty(k * n3, dtype=torch.float64, device=x.device)
     xb[:n3].copy_(x.reshape(-1))
     for i, sc in enumerate(scales):
@@ -346,18 +349,43 @@ def _sync_time(fn):
     return out, t[0].elapsed_time(t[1]) / 1e3
 
 
+def random_directions(seed: int):
+    """A control for the evaluation: the network's per-atom displacement
+    lengths in uniformly random directions (seeded torch generator)."""
+    def transform(y: torch.Tensor) -> torch.Tensor:
+        g = torch.Generator(device=y.device)
+        g.manual_seed(seed)
+        r = torch.randn((y.shape[0], 3), generator=g, device=y.device, dtype=torch.float32)
+        r = r / r.norm(dim=1, keepdim=True) * y[:, :3].norm(dim=1, keepdim=True)
+        out = torch.zeros_like(y)
+        out[:, :3] = r
+        return out
+    return transform
+
+
+def race_length(n_atoms: int) -> int:
+    """Iterations of the race for a system of n_atoms: a displaced start
+    needs longer to relieve its clashes in a larger system (measured: 200
+    suffice at 2,000 atoms, 1,000 are needed at 10,000)."""
+    return min(1000, max(200, n_atoms // 10))
+
+
 def evaluate(net: Net, systems, ctx_factory, tol: float = 1e-3, max_iter: int = 60000, precision="fp32",
-             scales=(0.5, 1.0), probe_iters: int = 200, control: bool = True, device="cuda",
-             log=None) -> list[dict]:
+             scales=(0.5, 1.0), probe_iters: int | None = None, control: bool = True, random_control: bool = False,
+             device="cuda", log=None) -> list[dict]:
     """Time to |grad E|_inf < tol of each system alone: plain L-BFGS from its
     stored start, and the learned start (probe_start) followed by L-BFGS
     from the winner, with features, network, the race and the final run all
     inside the timed region.  With `control`, also L-BFGS restarted after
     probe_iters iterations from the stored start alone (what the race does
-    without the network).  Contexts are built outside the timed regions;
-    each time is bracketed by device synchronisations."""
+    without the network); with `random_control`, the same race with the
+    network's displacement lengths in random directions.  Contexts are built outside the timed regions;
+    each time is bracketed by device synchronisations.  probe_iters=None
+    takes race_length(n_atoms) per system."""
     rows = []
+    fixed_probe = probe_iters
     for i, s in enumerate(systems):
+        probe_iters = fixed_probe if fixed_probe is not None else race_length(int(s["n_atoms"]))
         ctx = ctx_factory(s)
         pctx = ctx_factory([s] * (1 + len(scales)))
         sa = SystemArrays([s], device)
@@ -365,14 +393,16 @@ def evaluate(net: Net, systems, ctx_factory, tol: float = 1e-3, max_iter: int = 
         xp = x0.clone()
         rp, tp = _sync_time(lambda: ctx.minimize(xp, "lbfgs", tol=tol, max_iter=max_iter, precision=precision))
 
-        def learned():
-            xw, best, pres = probe_start(pctx, sa, net, x0, scales, probe_iters, tol, precision)
+        def raced(transform=None):
+            xw, best, pres = probe_start(pctx, sa, net, x0, scales, probe_iters, tol, precision, transform)
             xw = xw.contiguous()
             if pres[best]["term"] == 0:
                 return pres[best], best, pres, 0
             r = ctx.minimize(xw, "lbfgs", tol=tol, max_iter=max_iter - probe_iters, precision=precision)
             return r, best, pres, r["iters"]
-        (rl, best, pres, more), tl = _sync_time(learned)
+        (rl, best, pres, more), tl = _sync_time(raced)
+        if random_control:
+            (rr, best_r, pres_r, more_r), tr = _sync_time(lambda: raced(random_directions(1000 + i)))
         if control:
             xc = x0.clone()
 
@@ -388,16 +418,21 @@ def evaluate(net: Net, systems, ctx_factory, tol: float = 1e-3, max_iter: int = 
                    learned_time=tl, learned_iters=pres[best]["iters"] + more,
                    learned_evals=sum(r["evals"] for r in pres) + (rl["evals"] if more else 0),
                    learned_term=rl["term_name"], learned_energy=rl["energy"], learned_grad_inf=rl["grad_inf"],
-                   scale_taken=(0.0 if best == 0 else float(scales[best - 1])),
+                   scale_taken=(0.0 if best == 0 else float(scales[best - 1])), race_iters=probe_iters,
                    probe_energies=[r["energy"] for r in pres])
         if control:
             row.update(control_time=tc, control_iters=itc, control_term=rc["term_name"], control_energy=rc["energy"])
+        if random_control:
+            row.update(random_time=tr, random_iters=pres_r[best_r]["iters"] + more_r, random_term=rr["term_name"],
+                       random_energy=rr["energy"], random_winner=best_r)
         rows.append(row)
         if log:
             log(f"system {i} ({row['n']} atoms): plain {tp:.2f} s {rp['iters']} it {rp['term_name']} "
                 f"E {rp['energy']:.6e} | learned {tl:.2f} s {row['learned_iters']} it {rl['term_name']} "
                 f"E {rl['energy']:.6e} scale {row['scale_taken']}"
-                + (f" | restart {tc:.2f} s {itc} it {rc['term_name']} E {rc['energy']:.6e}" if control else ""))
+                + (f" | restart {tc:.2f} s {itc} it {rc['term_name']} E {rc['energy']:.6e}" if control else "")
+                + (f" | random {tr:.2f} s {rr['term_name']} E {rr['energy']:.6e} winner {best_r}"
+                   if random_control else ""))
         ctx.close()
         pctx.close()
     return rows
