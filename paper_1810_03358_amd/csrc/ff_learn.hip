@@ -175,21 +175,143 @@ __global__ void k_splitk_reduce(int m, int n, int slices, const float* __restric
 constexpr int kMaxSlices = 64;
 constexpr long kSplitFloats = (long)kMaxSlices * FF_LEARN_HIDDEN * FF_LEARN_HIDDEN;
 
+// LDS-tiled product for operands whose elements run contiguously along k
+// or along the other index (every product of the network): a workgroup
+// computes a 64 x 64 block of C from 64 x 32 tiles of A and 32 x 64 tiles of
+// B staged in LDS with 16-byte loads, each of its four wavefronts a 32 x 32
+// quarter (2 x 2 matrix-core tiles) reading 8-byte fragments.  Both tiles are
+// kept k-contiguous in LDS: element (r, k) at r * kLdk + k, rows padded to 40
+// values so that the 16 rows a fragment read touches fall on different banks.
+// A_K: A(i, k) = A[i * sa + k], else A[k * sa + i]; B_K: B(k, j) = B[j * sb + k],
+// else B[k * sb + j].  Out-of-range elements load as zero.  k slices, the
+// epilogue and the partial sums P as in k_gemm; kc is a multiple of 32.
+constexpr int kGbm = 64, kGbn = 64, kGbk = 32, kLdk = kGbk + 8;
+
+template <bool KCONT>
+__device__ __forceinline__ void stage_tile(const uint16_t* __restrict__ g, long st, int r0, int r_end, int k0,
+                                           int k_end, bool vec_ok, uint16_t* __restrict__ lds) {
+    const int t = threadIdx.x;
+    uint16_t v[8];
+    if (KCONT) {
+        // 64 rows x 32 k: thread t loads k [seg, seg + 8) of row t / 4
+        const int r = t >> 2, seg = (t & 3) * 8;
+        const int row = r0 + r, k = k0 + seg;
+        if (vec_ok && row < r_end && k + 8 <= k_end) {
+            *(uint4*)v = *(const uint4*)(g + row * st + k);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = (row < r_end && k + q < k_end) ? g[row * st + k + q] : (uint16_t)0;
+        }
+        *(uint4*)(lds + r * kLdk + seg) = *(const uint4*)v;
+    } else {
+        // 32 k x 64 rows: thread t loads rows [seg, seg + 8) of k = t / 8
+        const int kk = t >> 3, seg = (t & 7) * 8;
+        const int k = k0 + kk, row = r0 + seg;
+        if (vec_ok && k < k_end && row + 8 <= r_end) {
+            *(uint4*)v = *(const uint4*)(g + k * st + row);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = (k < k_end && row + q < r_end) ? g[k * st + row + q] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lds[(seg + q) * kLdk + kk] = v[q];
+    }
+}
+
+template <bool A_K, bool B_K>
+__global__ void __launch_bounds__(256) k_gemm_lds(int m, int n, int kdim, int kc, const uint16_t* __restrict__ A,
+                                                  long sa, const uint16_t* __restrict__ B, long sb, int vec_ok,
+                                                  const float* __restrict__ bias, int relu, float* __restrict__ C,
+                                                  long ldc, uint16_t* __restrict__ Cb, long ldcb,
+                                                  float* __restrict__ P) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kGbm * kLdk];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kGbn * kLdk];
+    const int tiles_n = (n + kGbn - 1) / kGbn;
+    const int m0 = (int)(blockIdx.x / tiles_n) * kGbm, n0 = (int)(blockIdx.x % tiles_n) * kGbn;
+    const int k_lo = blockIdx.y * kc, k_hi = min(kdim, k_lo + kc);
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int fr = l & 15, fk = 4 * (l >> 4);
+    f32x4_t acc[2][2] = {};
+    for (int k0 = k_lo; k0 < k_hi; k0 += kGbk) {
+        stage_tile<A_K>(A, sa, m0, m, k0, k_hi, vec_ok, As);
+        stage_tile<B_K>(B, sb, n0, n, k0, k_hi, vec_ok, Bs);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kGbk; ks += 16) {
+            bf16x4_t af[2], bf[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                af[u] = *(const bf16x4_t*)(As + (wm + 16 * u + fr) * kLdk + ks + fk);
+                bf[u] = *(const bf16x4_t*)(Bs + (wn + 16 * u + fr) * kLdk + ks + fk);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int w = 0; w < 2; ++w)
+                    acc[u][w] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[u], bf[w], acc[u][w], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = m0 + wm + 16 * u + fk + q, col = n0 + wn + 16 * w + fr;
+                if (r >= m || col >= n) continue;
+                float v = acc[u][w][q];
+                if (P) {
+                    P[((long)blockIdx.y * m + r) * n + col] = v;
+                    continue;
+                }
+                if (bias) v += bias[col];
+                if (relu) v = fmaxf(v, 0.0f);
+                if (C) C[r * ldc + col] = v;
+                if (Cb) Cb[r * ldcb + col] = to_bf16(v);
+            }
+}
+
 hipError_t launch_gemm(int m, int n, int k, const uint16_t* A, long sa0, long sa1, const uint16_t* B, long sb0,
                        long sb1, const float* bias, int relu, float* C, long ldc, uint16_t* Cb, long ldcb,
                        hipStream_t s, float* split = nullptr, long split_floats = 0) {
-    const long tiles = (long)((m + 15) / 16) * ((n + 15) / 16);
+    // the tiled kernel takes operands contiguous along one index, blocks of
+    // at least 64 x 64 x 32; 16-byte loads where strides and bases allow
+    const bool a_k = sa1 == 1, a_m = sa0 == 1 && !a_k, b_k = sb0 == 1, b_n = sb1 == 1 && !b_k;
+    const bool tiled = (a_k || a_m) && (b_k || b_n) && m >= kGbm && n >= kGbn && k >= kGbk;
+    const long blocks = tiled ? (long)((m + kGbm - 1) / kGbm) * ((n + kGbn - 1) / kGbn)
+                              : ((long)((m + 15) / 16) * ((n + 15) / 16) + 3) / 4;
     int slices = 1;
-    // split k when the tiles alone cannot fill the chip: slices of >= 256
-    if (split && tiles < 1024 && k >= 512) {
+    // split k when the output blocks alone cannot fill the chip: slices of >= 256
+    if (split && blocks < 256 && k >= 512) {
         const long by_k = k / 256, by_ws = split_floats / ((long)m * n);
         slices = (int)std::max(1L, std::min({by_k, by_ws, (long)kMaxSlices}));
     }
-    const int kc = slices == 1 ? k : ((k + slices - 1) / slices + 15) / 16 * 16;
+    const int step = tiled ? kGbk : 16;
+    const int kc = slices == 1 ? k : ((k + slices - 1) / slices + step - 1) / step * step;
     slices = (k + kc - 1) / kc;
     float* P = slices > 1 ? split : nullptr;
-    hipLaunchKernelGGL(k_gemm, dim3((unsigned)((tiles + 3) / 4), (unsigned)slices), dim3(256), 0, s, m, n, k, kc, A,
-                       sa0, sa1, B, sb0, sb1, bias, relu, C, ldc, Cb, ldcb, P);
+    if (tiled) {
+        const long sa = a_k ? sa0 : sa1, sb = b_k ? sb1 : sb0;
+        const int vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && sa % 8 == 0 && sb % 8 == 0;
+        const dim3 grid((unsigned)blocks, (unsigned)slices);
+        if (a_k && b_k)
+            hipLaunchKernelGGL((k_gemm_lds<true, true>), grid, dim3(256), 0, s, m, n, k, kc, A, sa, B, sb, vec, bias,
+                               relu, C, ldc, Cb, ldcb, P);
+        else if (a_k)
+            hipLaunchKernelGGL((k_gemm_lds<true, false>), grid, dim3(256), 0, s, m, n, k, kc, A, sa, B, sb, vec, bias,
+                               relu, C, ldc, Cb, ldcb, P);
+        else if (b_k)
+            hipLaunchKernelGGL((k_gemm_lds<false, true>), grid, dim3(256), 0, s, m, n, k, kc, A, sa, B, sb, vec, bias,
+                               relu, C, ldc, Cb, ldcb, P);
+        else
+            hipLaunchKernelGGL((k_gemm_lds<false, false>), grid, dim3(256), 0, s, m, n, k, kc, A, sa, B, sb, vec,
+                               bias, relu, C, ldc, Cb, ldcb, P);
+    } else {
+        hipLaunchKernelGGL(k_gemm, dim3((unsigned)blocks, (unsigned)slices), dim3(256), 0, s, m, n, k, kc, A, sa0, sa1,
+                           B, sb0, sb1, bias, relu, C, ldc, Cb, ldcb, P);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !P) return e;
     const long mn = (long)m * n;

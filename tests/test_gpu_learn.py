@@ -67,7 +67,11 @@ def _bf16_dev(a):
 
 @pytest.mark.parametrize("m,n,k,trans_a,trans_b", [
     (1, 1, 1, False, False), (17, 33, 45, False, False), (130, 16, 128, True, False),
-    (64, 128, 4099, True, False), (300, 128, 16, False, True), (16, 16, 16, True, True)])
+    (64, 128, 4099, True, False), (300, 128, 16, False, True), (16, 16, 16, True, True),
+    # the LDS-tiled kernel (blocks of 64 x 64 x 32): every layout, ragged edges,
+    # strides that do and do not allow 16-byte loads
+    (64, 64, 32, False, False), (200, 128, 128, False, False), (64, 128, 300, True, False),
+    (256, 64, 96, False, True), (129, 192, 70, True, True), (1000, 128, 45, False, False)])
 def test_gemm_is_exact_on_small_integers(m, n, k, trans_a, trans_b):
     """Integer operands in [-8, 8]: every product and partial sum is exact in
     FP32 (|sum| <= 64 k < 2^24), so any accumulation order gives the same C."""
