@@ -35,8 +35,9 @@
 //  - stop when |g|_inf < tol at the current point (FGM: the best point) or
 //    after max_iter iterations.
 // In FF_FP32_ACC64 mode the run switches to FP64 evaluations once both line
-// searches fail in FP32 or |g|_inf < 10 tol, decides convergence only on
-// FP64 gradients and re-evaluates the returned point in FP64.
+// searches fail in FP32, an accepted FP32 step lowers E by less than
+// 2^-20 |E|, or |g|_inf < 10 tol; it decides convergence only on FP64
+// gradients and re-evaluates the returned point in FP64.
 #pragma once
 #include "ff_internal.h"
 
@@ -119,6 +120,9 @@ __device__ inline void escalate(Ctl* c, int slot) {
     c->prec_now = P_FP64;
     c->phase = PH_REEVAL64;
     c->steepest = 1;
+    // a restart: the next search starts from h_init, not from the last
+    // FP32 step (which may have shrunk to the FP32 noise level)
+    c->h_prev = c->p.h_init;
     lbfgs_clear(c);
     if (c->p.method == M_OGM) ogm_restart(c);
     request_eval(c, PM_USE, slot, 0);
@@ -310,7 +314,10 @@ __device__ inline void begin_iteration(Ctl* c) {
         return;
     }
     if (c->iters >= c->iters_limit) { finish(c, T_MAX_ITER); return; }
-    if (p.precision == P_FP32 && !c->escalated && c->ginf[c->cur] < 10.0 * p.tol) { escalate(c, c->cur); return; }
+    if (p.precision == P_FP32 && !c->escalated && (c->ginf[c->cur] < 10.0 * p.tol || c->stall32)) {
+        escalate(c, c->cur);
+        return;
+    }
     c->write_r = 0;
     switch (p.method) {
     case M_GD:
@@ -424,6 +431,13 @@ __device__ inline void fgm_after_momentum(Ctl* c) {
 }
 
 __device__ void ls_success(Ctl* c, int slot, double h) {
+    // FP32 mode: a decrease below 2^-20 |E| (about ten times the FP32
+    // error of the energy) is within the rounding of the comparison, so the
+    // next iteration switches to FP64
+    if (c->p.precision == P_FP32 && !c->escalated && c->ls_base >= 0 && c->slot_prec[slot] == P_FP32) {
+        const double f0 = c->e[c->ls_base];
+        if (f0 - c->e[slot] < fabs(f0) * 0x1p-20) c->stall32 = 1;
+    }
     c->h_prev = fabs(h);
     c->accept_h = h;
     c->accept = 1;

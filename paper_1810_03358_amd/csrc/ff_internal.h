@@ -112,6 +112,7 @@ struct Ctl {
     int32_t cur, prev_x, best, w;          // slots
     int32_t prec_now;                      // precision of the running phase
     int32_t escalated;
+    int32_t stall32;                       // an FP32 step gained less than FP32 can resolve
     double h_prev;
     // line search
     int32_t ls_kind, ls_hstage, ls_base, ls_best, ls_ntrials, ls_primary, ls_fallback_done;

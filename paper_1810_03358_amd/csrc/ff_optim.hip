@@ -556,6 +556,7 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
     c->ls_best = -1;
     c->prec_now = p.precision;
     c->escalated = 0;
+    c->stall32 = 0;
     c->h_prev = p.h_init;
     c->steepest = 1;
     c->theta_prev = 1.0;

@@ -216,3 +216,18 @@ def test_fp64_ogm_iterates_match_the_oracle(system):
     # a one-ulp perturbation grows to 1.4e-13 (chain512) and 9e-10 (torsion300)
     # by iteration 50 in the oracle itself
     compare_traces(tr, ref, 50, tight=50 if system == "chain512" else 10)
+
+
+def test_fp32_stagnation_switches_to_fp64_and_converges():
+    """A compacted 595-atom chain on which FP32 line searches end up
+    accepting steps of 1e-9 A on FP32 noise: the run must switch to FP64,
+    restart its step length and converge (it used to stop with LS_FAILED at
+    |g|_inf = 0.13)."""
+    rng = np.random.default_rng(11)
+    sizes = rng.integers(300, 600, size=56)
+    s = chain_system(int(sizes[48]), 500_048, compact=True)
+    r, x, _, _ = gpu_run(s, "lbfgs", max_iter=30000, precision="fp32")
+    assert r["term"] == ff.FF_CONVERGED and r["evals_fp64"] >= 1
+    e_ref, g_ref = oracle.energy_grad(s, x)
+    assert np.abs(g_ref).max() < 1e-3
+    assert r["energy"] == pytest.approx(e_ref, rel=1e-9)
