@@ -36,7 +36,7 @@
 //    after max_iter iterations.
 // In FF_FP32_ACC64 mode the run switches to FP64 evaluations once both line
 // searches fail in FP32, an accepted FP32 step lowers E by less than
-// 2^-20 |E|, or |g|_inf < 10 tol; it decides convergence only on FP64
+// 2^-23 |E|, or |g|_inf < 10 tol; it decides convergence only on FP64
 // gradients and re-evaluates the returned point in FP64.
 #pragma once
 #include "ff_internal.h"
@@ -431,12 +431,12 @@ __device__ inline void fgm_after_momentum(Ctl* c) {
 }
 
 __device__ void ls_success(Ctl* c, int slot, double h) {
-    // FP32 mode: a decrease below 2^-20 |E| (about ten times the FP32
-    // error of the energy) is within the rounding of the comparison, so the
-    // next iteration switches to FP64
+    // FP32 mode: a decrease below 2^-23 |E| (twice the FP32 unit roundoff;
+    // the measured FP32 error of E is about 1e-7 |E|) cannot be told from
+    // rounding, so the next iteration switches to FP64
     if (c->p.precision == P_FP32 && !c->escalated && c->ls_base >= 0 && c->slot_prec[slot] == P_FP32) {
         const double f0 = c->e[c->ls_base];
-        if (f0 - c->e[slot] < fabs(f0) * 0x1p-20) c->stall32 = 1;
+        if (f0 - c->e[slot] < fabs(f0) * 0x1p-23) c->stall32 = 1;
     }
     c->h_prev = fabs(h);
     c->accept_h = h;
