@@ -5,7 +5,7 @@
  * Not part of the paper.  The paper minimizes the same force field from many
  * clashing poses (sections 3 and 5.3); this part learns, from (start,
  * minimum) pairs that ff_minimize itself produces, a per-atom displacement
- * that is applied to a start before L-BFGS.  The minimizer stays the judge:
+ * that is applied to a start before L-BFGS.  The minimizer keeps the last word:
  * a displaced start is kept per system only where the energy prefers it
  * (ff_learn_select compares two points of every system).
  *

@@ -2,7 +2,7 @@
 // nearest atoms of the same system, a 3-layer perceptron (BF16 weights and
 // activations, FP32 accumulation on the matrix cores) that predicts a
 // displacement of every atom, its training kernels, and the application of
-// the displacement before a minimization.  The minimizer stays the judge: a
+// the displacement before a minimization.  The minimizer keeps the last word: a
 // displaced start is kept per system only where the energy prefers it.
 #include <hip/hip_runtime.h>
 
