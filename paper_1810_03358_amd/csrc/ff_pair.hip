@@ -469,6 +469,15 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
 
 // ---------------------------------------------------------------- FP64 pairs
 
+// 1/sqrt(x) for finite x > 0: v_rsq_f64, then y (1 + e/2 + 3e^2/8) with
+// e = 1 - x y^2 (the error of the estimate enters cubed), the same
+// arithmetic rsqrt uses for such x.
+__device__ __forceinline__ double rsqrt_finite(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 template <int IPL, bool MASKED, bool FAR = false>
 __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const double2* __restrict__ s_c,
                                        int lane, int J0, const double (&xi)[IPL], const double (&yi)[IPL],
@@ -493,7 +502,11 @@ __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const d
                 if (FAR) ex = ex || ((fmask[k] >> (js & (kTile - 1))) & 1ull);
                 r2 = (delta > 0 && !ex) ? r2 : __builtin_inf();
             }
-            const double rinv = rsqrt(r2);
+            // unmasked tiles hold no excluded pair, so r2 is finite and
+            // positive (or 0 for coincident atoms, which gives a non-finite
+            // energy either way): the hardware estimate and one correction
+            // step, without the special-value handling rsqrt adds
+            const double rinv = MASKED ? rsqrt(r2) : rsqrt_finite(r2);
             const double rinv2 = rinv * rinv;
             const double rinv6 = rinv2 * rinv2 * rinv2;
             const double e6 = c6i[k] * cj.y * rinv6;
