@@ -384,9 +384,10 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel_ms": ms_pair,
             "flops_per_pair": FLOPS_PER_PAIR,
-            "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
         },
     }
+    if args.precision == "fp32":
+        out["roofline"]["frac_of_packed_fp32_peak"] = achieved / PEAK_FP32_PACKED_TFLOPS
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, s["x"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
