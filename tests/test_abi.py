@@ -198,3 +198,12 @@ def test_learn_entry_points_reject_bad_arguments_on_the_host():
     assert lib.ff_learn_select(1, 0, p, p, p, p, p, p, nul, nul, nul) == ff.FF_ERR_ARG
     assert lib.ff_learn_to_bf16(p, 0, p, nul) == ff.FF_ERR_ARG
     assert lib.ff_learn_delta(p, nul, 4, p, nul) == ff.FF_ERR_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(INCLUDE)
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
