@@ -613,8 +613,13 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
 
 // The FP64 kernel walks the chunks with a grid stride: in FP32 mode (and in
 // cycles without an evaluation) its workgroups only check and exit, and a
-// capped grid keeps that cheap.
-constexpr int kPair64Grid = 4096;
+// capped grid keeps that cheap.  The cap allows 16384 wavefronts (four per
+// SIMD) and at least 4096 workgroups: one-wavefront workgroups (the batch
+// tiling) would otherwise leave three quarters of the chip idle.
+constexpr int kPair64Waves = 16384;
+__host__ __device__ constexpr int pair64_grid_cap(int waves) {
+    return kPair64Waves / waves > 4096 ? kPair64Waves / waves : 4096;
+}
 
 template <int WAVES, int IPL>
 __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
@@ -642,7 +647,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
             hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32, true>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
         else if (prec)                                                                                \
             hipLaunchKernelGGL((k_pair32<T.waves32, T.ipl32, false>), dim3(grid), dim3(64 * T.waves32), 0, s, a); \
-        else hipLaunchKernelGGL((k_pair64<T.waves64, T.ipl64>), dim3(grid < kPair64Grid ? grid : kPair64Grid), \
+        else hipLaunchKernelGGL((k_pair64<T.waves64, T.ipl64>),                                        \
+                                dim3(grid < pair64_grid_cap(T.waves64) ? grid : pair64_grid_cap(T.waves64)), \
                                 dim3(64 * T.waves64), 0, s, a);                                                 \
         break;                                                                                     \
     }
