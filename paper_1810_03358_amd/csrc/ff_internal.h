@@ -162,6 +162,7 @@ constexpr TileConfig kTileConfigs[] = {
     {256, 2, 2, 4, 1},    // 4
     {128, 2, 1, 2, 1},    // 5
     {128, 1, 2, 2, 1},    // 6
+    {256, 2, 2, 2, 2},    // 7: as 4, with two atoms per lane in FP64 too
 };
 constexpr int kNumTileConfigs = sizeof(kTileConfigs) / sizeof(kTileConfigs[0]);
 

@@ -663,6 +663,7 @@ hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
         FF_PAIR_CASE(4)
         FF_PAIR_CASE(5)
         FF_PAIR_CASE(6)
+        FF_PAIR_CASE(7)
     default:
         return hipErrorInvalidValue;
     }
