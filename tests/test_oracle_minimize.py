@@ -422,3 +422,160 @@ def test_ogm_converges_on_an_ill_conditioned_quadratic():
     r = minimize(quad(lam, b), np.zeros(60), MinParams(method=oracle.OGM, tol=1e-7, max_iter=2000))
     assert r.term == oracle.CONVERGED
     np.testing.assert_allclose(r.x, b / lam, rtol=0, atol=1e-6)
+
+
+# ------------------------------------------- CG beta at non-orthogonal gradients
+
+def test_cg_beta_values_by_hand_at_non_orthogonal_gradients():
+    """Every beta of section 5.1 at one (g_k, g_{k+1}, d_k) where the seven
+    formulas give six different values, each worked out by hand:
+    g = (1, 0), g+ = (1, 2), d = (-3, 1), so y = g+ - g = (0, 2),
+    <g+, y> = 4, |g+|^2 = 5, |g|^2 = 1, <d, y> = 2, -<d, g> = 3.
+    A swapped numerator or denominator between any two variants changes
+    the value."""
+    g, gn, d = np.array([1.0, 0.0]), np.array([1.0, 2.0]), np.array([-3.0, 1.0])
+    expect = {oracle.CG_PRP: 4.0,         # <g+, y> / |g|^2
+              oracle.CG_FR: 5.0,          # |g+|^2 / |g|^2
+              oracle.CG_HS: 2.0,          # <g+, y> / <d, y>
+              oracle.CG_PRP_PLUS: 4.0,    # max(0, PRP)
+              oracle.CG_CD: 5.0 / 3.0,    # |g+|^2 / (-<d, g>)
+              oracle.CG_LS: 4.0 / 3.0,    # <g+, y> / (-<d, g>)
+              oracle.CG_DY: 2.5}          # |g+|^2 / <d, y>
+    for v, b in expect.items():
+        assert oracle.cg_beta(v, g, gn, d) == b, v
+
+
+def test_cg_beta_prp_plus_clamps_a_negative_prp():
+    """g = (2, 0), g+ = (1, 0.5): y = (-1, 0.5), <g+, y> = -0.75, |g|^2 = 4,
+    so PRP = -0.1875 while PRP+ = 0."""
+    g, gn, d = np.array([2.0, 0.0]), np.array([1.0, 0.5]), np.array([-2.0, 0.0])
+    assert oracle.cg_beta(oracle.CG_PRP, g, gn, d) == -0.1875
+    assert oracle.cg_beta(oracle.CG_PRP_PLUS, g, gn, d) == 0.0
+    # the same point through the other denominators: <d, y> = 2, -<d, g> = 4
+    assert oracle.cg_beta(oracle.CG_HS, g, gn, d) == -0.375
+    assert oracle.cg_beta(oracle.CG_LS, g, gn, d) == -0.1875
+    assert oracle.cg_beta(oracle.CG_DY, g, gn, d) == 0.625
+    assert oracle.cg_beta(oracle.CG_CD, g, gn, d) == 0.3125
+    assert oracle.cg_beta(oracle.CG_FR, g, gn, d) == 0.3125
+
+
+def test_cg_beta_zero_denominators_restart():
+    g, gn = np.array([1.0, 0.0]), np.array([1.0, 2.0])
+    d_perp_y = np.array([1.0, 0.0])            # <d, y> = 0: HS and DY restart
+    assert oracle.cg_beta(oracle.CG_HS, g, gn, d_perp_y) == 0.0
+    assert oracle.cg_beta(oracle.CG_DY, g, gn, d_perp_y) == 0.0
+    d_perp_g = np.array([0.0, 1.0])            # <d, g> = 0: CD and LS restart
+    assert oracle.cg_beta(oracle.CG_CD, g, gn, d_perp_g) == 0.0
+    assert oracle.cg_beta(oracle.CG_LS, g, gn, d_perp_g) == 0.0
+    z = np.zeros(2)                            # |g| = 0: PRP, FR, PRP+ restart
+    for v in (oracle.CG_PRP, oracle.CG_FR, oracle.CG_PRP_PLUS):
+        assert oracle.cg_beta(v, z, gn, d_perp_y) == 0.0
+
+
+# ------------------------------------------------------- LS_PAR branch by branch
+
+def _slice(f):
+    """A 1-D objective f(h) along r = e_1 from x = 0, recording its probes."""
+    probes = []
+
+    def fg(x):
+        h = float(x[0])
+        probes.append(h)
+        v = f(h)
+        return v, np.array([0.0])
+
+    return fg, probes
+
+
+def test_ls_par_vertex_clamped_at_ten_h1():
+    """f(h) = -h + h^2/1024 (f* = 0, slope -1): the first parabola is f
+    itself, with vertex 512 h1, so the second trial is clamped to 10 h1."""
+    fg, probes = _slice(lambda h: -h + h * h / 1024.0)
+    ok, h, f, _, hmin = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, K=2)
+    assert probes == [1.0, 10.0]
+    assert ok and h == 10.0 and f == -10.0 + 100.0 / 1024.0 and hmin == 1.0
+
+
+def test_ls_par_vertex_clamped_at_h1_over_100():
+    """f(h) = -h + 128 h^2: vertex at h1/256, clamped up to h1/100."""
+    fg, probes = _slice(lambda h: -h + 128.0 * h * h)
+    ok, h, f, _, hmin = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, K=2)
+    assert probes == [1.0, 0.01]
+    # f(0.01) = -0.01 + 0.0128 > 0 = f*: no decrease, the search fails
+    assert not ok and h == 0.0 and f == 0.0 and hmin == 0.01
+
+
+@pytest.mark.parametrize("curv", [0.0, -1.0])
+def test_ls_par_non_convex_first_parabola_grows_the_step(curv):
+    """f(h) = -h + curv h^2 with curv <= 0 (a = curv <= 0): the second trial
+    is k+ h1."""
+    fg, probes = _slice(lambda h: -h + curv * h * h)
+    ok, h, f, _, _ = oracle.ls_par(fg, np.zeros(1), np.ones(1), 0.25, 0.0, -1.0, K=2, k_plus=3.0)
+    assert probes == [0.25, 0.75]
+    assert ok and h == 0.75
+
+
+def test_ls_par_non_finite_first_trial_shrinks():
+    """f = inf beyond h = 0.5 (a clash): the second trial is k- h1."""
+    fg, probes = _slice(lambda h: math.inf if h > 0.5 else -h)
+    ok, h, f, _, hmin = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, K=2, k_minus=0.25)
+    assert probes == [1.0, 0.25]
+    assert ok and h == 0.25 and f == -0.25 and hmin == 0.25
+
+
+def test_ls_par_third_trial_on_a_concave_slice_takes_the_midpoint():
+    """K = 3 on f(h) = -h - h^2: trials 1 and then 2 (a < 0: k+ h1); the
+    parabola through the three best points (2, -6), (1, -2), (0, 0) is f
+    itself, concave, so the third trial is the midpoint of the best two,
+    1.5.  The best trial (h = 2) is returned."""
+    fg, probes = _slice(lambda h: -h - h * h)
+    ok, h, f, _, hmin = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, K=3)
+    assert probes == [1.0, 2.0, 1.5]
+    assert ok and h == 2.0 and f == -6.0 and hmin == 1.0
+
+
+def test_ls_par_third_trial_vertex_behind_the_base_takes_the_midpoint():
+    """K = 3 with G0 on f(h) = h^2 + h, an ascent slice handed a descent
+    slope: the parabola through the three best points has its vertex at
+    h = -0.5, behind the base point; the search stays on h > 0 and takes the
+    midpoint of the best two instead, then fails (no trial is below f*)."""
+    fg, probes = _slice(lambda h: h * h + h)
+    # slope -1 passed in (as if the gradient said descent): the first
+    # parabola through (0, 0), slope -1 and (1, 2) has a = 3 and vertex 1/6
+    ok, h, f, _, _ = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, K=3)
+    h2 = min(max(1.0 / 6.0, 0.01), 10.0)
+    assert probes[:2] == [1.0, h2]
+    # best three: (0, 0), (1/6, 0.1944), (1, 2): their parabola is f itself,
+    # vertex -0.5 < 0, so the third trial is the midpoint of 0 and 1/6
+    assert probes[2] == 0.5 * (0.0 + h2)
+    assert not ok and h == 0.0
+
+
+def test_ls_par_ties_rank_the_smaller_step_first():
+    """Two trials with equal energy: the smaller step wins."""
+    vals = {1.0: -1.0, 2.0: -1.0}
+    fg, probes = _slice(lambda h: vals[h])
+    # f1 = -1 at h1 = 1 with slope -1: a = 0, so the second trial is 2 h1
+    ok, h, f, _, _ = oracle.ls_par(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, K=2)
+    assert probes == [1.0, 2.0] and ok and h == 1.0 and f == -1.0
+
+
+def test_ls_h_equal_energy_keeps_shrinking():
+    """LS_H accepts only a strict decrease: on a flat slice f = f* it shrinks
+    down to eps_h and fails."""
+    fg, probes = _slice(lambda h: 0.0)
+    ok, h, f, _ = oracle.ls_h(fg, np.zeros(1), np.ones(1), 1.0, 0.0, 2.0, 0.5, 1e-3)
+    assert not ok and h == 0.0
+    assert probes == [1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625, 0.0078125, 0.00390625, 0.001953125]
+
+
+def test_failed_ls_par_falls_back_to_ls_h_from_the_smallest_trial():
+    """f(h) = -h + 128 h^2 from h0 = 1: LS_PAR tries 1 and 0.01 and finds no
+    decrease (f(0.01) = 0.0028 > 0); the fallback LS_H starts at the smallest
+    trial step 0.01, fails there again and halves to 0.005, where
+    f = -0.0018 < 0."""
+    from oracle.minimize import _search
+    fg, probes = _slice(lambda h: -h + 128.0 * h * h)
+    ok, h, f, _ = _search(fg, np.zeros(1), np.ones(1), 1.0, 0.0, -1.0, MinParams(method=oracle.LBFGS))
+    assert probes == [1.0, 0.01, 0.01, 0.005]
+    assert ok and h == 0.005 and f == -0.005 + 128.0 * 0.005 * 0.005
