@@ -54,6 +54,8 @@ def _load():
                                               C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)]
         lib.oracle_atom_gradients.restype = C.c_int
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_abs_pair_force.argtypes = [C.POINTER(_CSystem), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        lib.oracle_abs_pair_force.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -120,6 +122,19 @@ def atom_gradients(sys, x, atoms):
     rc = _load().oracle_atom_gradients(C.byref(s.c), _dptr(x), _iptr(atoms), len(atoms), _dptr(out))
     if rc != 0:
         raise ValueError(f"oracle_atom_gradients failed ({rc})")
+    return out
+
+
+def abs_pair_force(sys, x):
+    """Per atom, the sum over its non-excluded partners of |dE_ij/dr|: the
+    scale against which rounding errors of a gradient component are stated
+    (test tolerances only)."""
+    s = _as_system(sys)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(s.n, 3)
+    out = np.zeros(s.n)
+    rc = _load().oracle_abs_pair_force(C.byref(s.c), _dptr(x), _dptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_abs_pair_force failed ({rc})")
     return out
 
 

@@ -324,6 +324,38 @@ int oracle_energy_grad(const oracle_system *s, const double *x, double *terms, d
     return 0;
 }
 
+/* Scale of the rounding error of atom i's nonbonded gradient: out[i] =
+ * sum over non-excluded j of |dE_ij/dr| (the magnitudes of the pair forces
+ * that are summed into atom i's gradient; Coulomb and Lennard-Jones parts
+ * added as magnitudes).  Test-side only: tolerances of reduced-precision
+ * sums are stated as multiples of it. */
+int oracle_abs_pair_force(const oracle_system *s, const double *x, double *out)
+{
+    if (validate(s)) return -1;
+    excl_t ex;
+    if (build_exclusions(s, &ex)) return -2;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t i = 0; i < s->n_atoms; ++i) {
+        double acc = 0.0;
+        for (int32_t j = 0; j < s->n_atoms; ++j) {
+            if (j == i || excluded(&ex, i, j)) continue;
+            double dx = x[3 * i] - x[3 * j];
+            double dy = x[3 * i + 1] - x[3 * j + 1];
+            double dz = x[3 * i + 2] - x[3 * j + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double c = s->coulomb_c * s->q[i] * s->q[j];
+            double sig = sqrt(s->sigma[i] * s->sigma[j]);
+            double eps = sqrt(s->eps[i] * s->eps[j]);
+            double sr = sig / r;
+            double sr6 = sr * sr * sr * sr * sr * sr;
+            acc += fabs(c) / (r * r) + 4.0 * eps * (12.0 * sr6 * sr6 + 6.0 * sr6) / r;
+        }
+        out[i] = acc;
+    }
+    free_exclusions(&ex);
+    return 0;
+}
+
 /* Gradient of the listed atoms only (out: [count][3]); O(N) per atom, for
  * spot checks of large systems. */
 int oracle_atom_gradients(const oracle_system *s, const double *x, const int32_t *atoms,

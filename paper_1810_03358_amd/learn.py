@@ -339,16 +339,6 @@ def probe_start(probe_ctx, sa: SystemArrays, net: Net, x: torch.Tensor, scales=(
     return xb[best * n3:(best + 1) * n3].reshape(-1, 3), best, res
 
 
-def _sync_time(fn):
-    torch.cuda.synchronize()
-    t = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t[0].record()
-    out = fn()
-    t[1].record()
-    torch.cuda.synchronize()
-    return out, t[0].elapsed_time(t[1]) / 1e3
-
-
 def random_directions(seed: int):
     """A control for the evaluation: the network's per-atom displacement
     lengths in uniformly random directions (seeded torch generator)."""

@@ -7,8 +7,11 @@ oracle's BF16 emulation: both round the same operands to BF16, but the GPU
 accumulates in FP32 in another order, so a rounded activation can land on
 the neighbouring BF16 value (one unit in the last place, at most 2^-7
 relative).  The forward test bounds each output by 2^-6 times the absolute
-products through which such a flip could reach it; gradients are compared per
-parameter block in relative 2-norm against BF16's unit roundoff 2^-8.
+products through which such a flip could reach it; on random inputs the
+gradients are compared per parameter block in relative 2-norm against BF16's
+unit roundoff 2^-8, and on inputs where every rounding and sum is exact
+(tests/learn_exact.py) the forward output and every gradient element must
+equal the oracle's.
 """
 import numpy as np
 import pytest
@@ -142,6 +145,27 @@ def test_backward_matches_the_oracle(rows):
         assert err <= 2.0 ** -8 * np.linalg.norm(gob[name]) + 1e-12, name
     # the padding columns of the output layer get exactly zero gradient
     assert np.all(gb["W3"][:, 3:] == 0) and np.all(gb["b3"][3:] == 0)
+
+
+@pytest.mark.parametrize("rows,seed", [(64, 1), (96, 2), (2, 3), (2050, 4)])
+def test_forward_and_backward_are_exact_on_exact_inputs(rows, seed):
+    """Element by element: a wrong index, transpose, mask or bias sum in any
+    of the six gradient blocks changes at least one value."""
+    from tests.learn_exact import exact_case
+    theta, fbits, T = exact_case(rows, seed)
+    net = L.Net(theta, device=DEV)
+    xb = torch.tensor(fbits.view(np.int16), device=DEV)
+    y = net.forward(xb).cpu().numpy().astype(np.float64)
+    X = OL.bf16_value(fbits)
+    yo, _ = OL.forward(theta.astype(np.float64), X, emulate=True)
+    np.testing.assert_array_equal(y, yo)
+    loss = net.loss_grad(xb, torch.tensor(T, device=DEV))
+    g = net.grad.cpu().numpy().astype(np.float64)
+    lo, go = OL.loss_grad(theta.astype(np.float64), X, T.astype(np.float64), emulate=True)
+    assert float(loss.cpu()[0]) == pytest.approx(lo, rel=1e-6)
+    gb, gob = OL.unpack(g), OL.unpack(go)
+    for name, _ in OL.SHAPES:
+        np.testing.assert_array_equal(gb[name], gob[name], err_msg=name)
 
 
 def test_adam_matches_the_oracle():

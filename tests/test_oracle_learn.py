@@ -166,3 +166,37 @@ def test_adam_first_step_and_convergence():
     for k in range(1, 3001):
         t, m, v = L.adam(t, 2 * (t - 2.0), m, v, k, lr=0.05)
     assert abs(t[0] - 2.0) < 1e-3
+
+
+
+@pytest.mark.parametrize("rows,seed", [(64, 1), (96, 2), (2, 3), (2050, 4)])
+def test_exact_case_has_no_rounding_anywhere(rows, seed):
+    """The inputs of the GPU's element-wise backward test (tests/learn_exact.py)
+    must be exact: the BF16-emulated gradient equals the FP64 one bit for bit,
+    the FP32 inputs hold the FP64 values, and the output layer's padding
+    columns get zero gradient."""
+    from tests.learn_exact import exact_case
+    theta, fbits, T = exact_case(rows, seed)
+    X = L.bf16_value(fbits)
+    t64 = theta.astype(np.float64)
+    l_e, g_e = L.loss_grad(t64, X, T.astype(np.float64), emulate=True)
+    l_x, g_x = L.loss_grad(t64, X, T.astype(np.float64), emulate=False)
+    np.testing.assert_array_equal(g_e, g_x)
+    assert l_e == l_x
+    ye, _ = L.forward(t64, X, emulate=True)
+    yx, c = L.forward(t64, X, emulate=False)
+    np.testing.assert_array_equal(ye, yx)
+    for k in ("H1", "H2"):
+        np.testing.assert_array_equal(L.bf16(c[k]), c[k])
+    g = L.unpack(g_x)
+    assert np.all(g["W3"][:, 3:] == 0) and np.all(g["b3"][3:] == 0)
+    # the gradient is not trivially zero in any block
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert np.count_nonzero(g[k]) > 0, k
+    # FP32 sums in another order give the same values: recompute with float32
+    f32 = np.float32
+    p = {k: v.astype(f32) for k, v in L.unpack(theta).items()}
+    H1 = np.maximum(X.astype(f32) @ p["W1"] + p["b1"], 0)
+    H2 = np.maximum(H1 @ p["W2"] + p["b2"], 0)
+    Y = H2 @ p["W3"] + p["b3"]
+    np.testing.assert_array_equal(Y.astype(np.float64), yx)
