@@ -106,6 +106,23 @@ def autotune(system, x: torch.Tensor, precision: str | int = "fp32", reps: int =
     return (cfg.value, ch.value), ms.value
 
 
+def _out_tensor(t, numel: int, x: torch.Tensor, name: str) -> torch.Tensor:
+    """An output buffer the kernels write numel float64 values into: checked
+    like the coordinates x (already checked to be a CUDA tensor), since the
+    kernels write through its raw pointer."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, not {t.dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, {numel} needed")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != x.device:
+        raise ValueError(f"{name} is on {t.device}, the coordinates on {x.device}")
+    return t
+
+
 class Context:
     """Prepared system(s) on one GPU: workspace (torch uint8 tensor) + ff_ctx.
 
@@ -169,11 +186,15 @@ class Context:
     def energy_grad(self, x: torch.Tensor, precision: str | int = "fp64", want_grad: bool = True,
                     out_e: torch.Tensor | None = None, out_g: torch.Tensor | None = None, stream=None):
         """E and grad E at x (device tensor [n_atoms, 3], float64).  Asynchronous
-        on the current stream; returns device tensors."""
+        on the current stream; returns device tensors (out_e: n_sys float64
+        entries, out_g: like x, if given)."""
         x = self._coords(x)
         prec = PRECISIONS.get(precision, precision)
-        e = out_e if out_e is not None else torch.empty(self.n_sys, dtype=torch.float64, device=x.device)
-        g = (out_g if out_g is not None else torch.empty_like(x)) if want_grad else None
+        e = _out_tensor(out_e, self.n_sys, x, "out_e") if out_e is not None else \
+            torch.empty(self.n_sys, dtype=torch.float64, device=x.device)
+        g = None
+        if want_grad:
+            g = _out_tensor(out_g, x.numel(), x, "out_g") if out_g is not None else torch.empty_like(x)
         _check(N.load().ff_energy_grad(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(e.data_ptr()),
                                        C.c_void_p(g.data_ptr()) if g is not None else None, int(prec),
                                        _stream_ptr(stream)), "ff_energy_grad")

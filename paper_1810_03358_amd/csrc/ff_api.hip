@@ -18,7 +18,6 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <string>
 #include <vector>
 
 #include "ff.h"
@@ -49,15 +48,17 @@ struct ff_ctx {
     int last_method = -1, last_m = -1, last_prec = -1;
 };
 
-static thread_local std::string g_err;
+// Text of the last error of this thread (fixed storage: no call allocates
+// host memory to report an error).
+static thread_local char g_err[512];
+
+static void clear_error() { g_err[0] = '\0'; }
 
 static ff_status fail(ff_status st, const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return st;
 }
 
@@ -70,15 +71,34 @@ static ff_status fail(ff_status st, const char* fmt, ...) {
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ layout
-// Excluded pairs (1-2 and 1-3) of one system that are more than kExclWindow
-// atoms apart, as (lower, higher) global padded indices.  Pairs with a bad
-// index or null arrays are skipped here (validation reports them).
-static void far_exclusions(const ff_system& s, int aoff, std::vector<std::pair<int, int>>& out) {
+// An excluded pair (1-2 or 1-3) more than kExclWindow atoms apart, as global
+// padded indices (lo < hi).
+struct FarPair { int32_t lo, hi; };
+
+// Host buffers make_layout and pack_static share: the far pairs and the
+// distinct pair units holding them.  `cap` entries each, at least
+// far_capacity() of the systems.
+struct FarTmp {
+    FarPair* pairs;
+    long long* keys;     // (I-block << 32 | j-tile), sorted, distinct
+    size_t cap;
+    size_t n_pairs = 0, n_keys = 0;
+};
+
+static size_t far_capacity(const ff_system* s, int32_t n_sys) {
+    size_t c = 0;
+    for (int k = 0; k < n_sys; ++k) c += (size_t)std::max(0, s[k].n_bonds) + (size_t)std::max(0, s[k].n_angles);
+    return std::max<size_t>(c, 1);
+}
+
+// Far exclusions of one system appended to ft.pairs.  Pairs with a bad index
+// or null arrays are skipped here (validation reports them).
+static void far_exclusions(const ff_system& s, int aoff, FarTmp& ft) {
     const int n = s.n_atoms;
     auto add = [&](int i, int j) {
         if (i < 0 || j < 0 || i >= n || j >= n || i == j) return;
         const int lo = std::min(i, j), hi = std::max(i, j);
-        if (hi - lo > kExclWindow) out.emplace_back(aoff + lo, aoff + hi);
+        if (hi - lo > kExclWindow && ft.n_pairs < ft.cap) ft.pairs[ft.n_pairs++] = FarPair{aoff + lo, aoff + hi};
     };
     if (s.bond)
         for (int b = 0; b < s.n_bonds; ++b) add(s.bond[2 * b], s.bond[2 * b + 1]);
@@ -86,25 +106,15 @@ static void far_exclusions(const ff_system& s, int aoff, std::vector<std::pair<i
         for (int a = 0; a < s.n_angles; ++a) add(s.angle[3 * a], s.angle[3 * a + 2]);
 }
 
-// Distinct pair units (I-block of the lower atom, j-tile of the higher one)
-// of a list of far exclusions, as sorted (row << 32 | tile) keys.
-static std::vector<long long> far_unit_keys(const std::vector<std::pair<int, int>>& far, int block) {
-    std::vector<long long> keys;
-    keys.reserve(far.size());
-    for (auto& p : far) keys.push_back(((long long)(p.first / block) << 32) | (long long)(p.second / kTile));
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-    return keys;
-}
-
 // Tile configuration: explicit (cfg >= 0, chunk >= 1), or by default a single
 // system picks its I-block by size and a batch of several systems uses 64-atom
-// I-blocks so that small systems are padded to a multiple of 64 only
-// ("FF_PAIR_CONFIG=cfg[,chunk]" overrides the default).
-static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, std::vector<SysInfo>* out,
-                        int32_t cfg_req = -1, int32_t chunk_req = 0) {
+// I-blocks so that small systems are padded to a multiple of 64 only.
+// `sys` receives n_sys entries; `ft` the far pairs and their units.
+// energy_only: no optimizer vectors (the layout serves ff_energy_grad only).
+static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, SysInfo* sys, FarTmp& ft,
+                        int32_t cfg_req = -1, int32_t chunk_req = 0, bool energy_only = false) {
     std::memset(&L, 0, sizeof L);
-    if (!s || n_sys < 1) return false;
+    if (!s || n_sys < 1 || !sys) return false;
     if (m_max < 0 || m_max > kMaxM) return false;
     long long n_tot = 0;
     int n_max = 0;
@@ -114,6 +124,7 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
         n_max = std::max(n_max, s[k].n_atoms);
     }
     if (n_tot > (1 << 28)) return false;
+    if (ft.cap < far_capacity(s, n_sys)) return false;
     L.n_sys = n_sys;
     // defaults from sweeps on MI355X: small systems and batches use 64-atom
     // blocks; large systems 256-atom blocks with two atoms per lane, and from
@@ -127,14 +138,8 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
         if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk) return false;
         L.cfg = cfg_req;
         L.chunk = chunk_req;
-    } else if (const char* env = std::getenv("FF_PAIR_CONFIG")) {
-        int cfg = -1, chunk = 0;
-        const int got = std::sscanf(env, "%d,%d", &cfg, &chunk);
-        if (got >= 1 && cfg >= 0 && cfg < kNumTileConfigs) L.cfg = cfg;
-        if (got == 2 && chunk >= 1 && chunk <= kMaxChunk) L.chunk = chunk;
     }
     L.block = kTileConfigs[L.cfg].block;
-    std::vector<SysInfo> sys(n_sys);
     int aoff = 0, uoff = 0, units = 0, chunks = 0, nbd = 0, nag = 0, ndh = 0, ebo = 0;
     size_t red = 0;
     L.acc_rows = std::max(1, m_max + 1);
@@ -190,21 +195,22 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.n_terms_slots = 2 * nbd + 3 * nag + 4 * ndh;
     L.n_bonded_blocks = ebo;
     L.n_fin_blocks = 0;
-    for (auto& si : sys) L.n_fin_blocks += si.fin_blocks;
-    {
-        std::vector<std::pair<int, int>> far;
-        for (int k = 0; k < n_sys; ++k) far_exclusions(s[k], sys[k].aoff, far);
-        L.n_far_units = (int32_t)far_unit_keys(far, L.block).size();
-    }
+    for (int k = 0; k < n_sys; ++k) L.n_fin_blocks += sys[k].fin_blocks;
+    ft.n_pairs = 0;
+    for (int k = 0; k < n_sys; ++k) far_exclusions(s[k], sys[k].aoff, ft);
+    for (size_t q = 0; q < ft.n_pairs; ++q)
+        ft.keys[q] = ((long long)(ft.pairs[q].lo / L.block) << 32) | (long long)(ft.pairs[q].hi / kTile);
+    std::sort(ft.keys, ft.keys + ft.n_pairs);
+    ft.n_keys = (size_t)(std::unique(ft.keys, ft.keys + ft.n_pairs) - ft.keys);
+    L.n_far_units = (int32_t)ft.n_keys;
     L.m_max = m_max;
     L.vstride = (3 * (size_t)L.np + 31) / 32 * 32;
     L.ctl_stride = align256(sizeof(Ctl));
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + std::max<size_t>(bytes, 1)); return r; };
     const size_t np = L.np;
-    L.off_batch = take(sizeof(BatchState));
+    // packed once per context (pack_static), read only afterwards
     L.off_sys = take((size_t)n_sys * sizeof(SysInfo));
-    L.off_ctl = take((size_t)n_sys * L.ctl_stride);
     L.off_c12 = take(np * 4);
     L.off_c6 = take(np * 4);
     L.off_q = take(np * 4);
@@ -214,38 +220,62 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.off_excl = take(np * 8);
     L.off_chunks = take((size_t)L.n_chunks * sizeof(ChunkInfo));
     L.off_rows = take((size_t)L.nb * sizeof(RowInfo));
-    L.off_pi = take((size_t)L.n_chunks * L.block * 3 * 8);
-    L.off_pj = take((size_t)L.n_units * kTile * 3 * 8);
-    L.off_ep = take((size_t)L.n_chunks * 8);
     L.off_bond = take((size_t)L.n_bonds * 8);
     L.off_bondp = take((size_t)L.n_bonds * 16);
     L.off_angle = take((size_t)L.n_angles * 12);
     L.off_anglep = take((size_t)L.n_angles * 16);
     L.off_dih = take((size_t)L.n_dihedrals * 16);
     L.off_dihp = take((size_t)L.n_dihedrals * 32);
-    L.off_fb = take((size_t)L.n_terms_slots * 24);
-    L.off_eb = take((size_t)L.n_bonded_blocks * 8);
     L.off_inc_start = take((np + 1) * 4);
     L.off_inc = take((size_t)L.n_terms_slots * 4);
-    L.off_red = take(red * 8);
-    L.off_vec = take((size_t)V_COUNT * L.vstride * 8 + (size_t)kTraceCap * 3 * 8);
     L.off_map_fin = take((size_t)L.n_fin_blocks * 8);
     L.off_map_vec = take((size_t)L.n_vec_blocks * 8);
     L.off_map_bonded = take((size_t)L.n_bonded_blocks * 8);
     L.off_map_acc = take((size_t)L.n_acc_blocks * 8);
     L.off_far_unit = take((size_t)L.n_units * 4);
     L.off_far_mask = take((size_t)L.n_far_units * L.block * 8);
+    L.static_end = o;
+    // written by the kernels
+    L.off_batch = take(sizeof(BatchState));
+    L.off_ctl = take((size_t)n_sys * L.ctl_stride);
+    L.off_pi = take((size_t)L.n_chunks * L.block * 3 * 8);
+    L.off_pj = take((size_t)L.n_units * kTile * 3 * 8);
+    L.off_ep = take((size_t)L.n_chunks * 8);
+    L.off_fb = take((size_t)L.n_terms_slots * 24);
+    L.off_eb = take((size_t)L.n_bonded_blocks * 8);
+    L.off_red = take(red * 8);
+    L.off_vec = take(energy_only ? 0 : (size_t)V_COUNT * L.vstride * 8 + (size_t)kTraceCap * 3 * 8);
     L.total = o;
-    if (out) *out = std::move(sys);
     return true;
+}
+
+// make_layout with its host storage on the heap.
+struct LayoutHost {
+    std::vector<SysInfo> sys;
+    std::vector<FarPair> pairs;
+    std::vector<long long> keys;
+    FarTmp ft{nullptr, nullptr, 0};
+};
+
+static bool layout_heap(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, LayoutHost& h,
+                        int32_t cfg_req = -1, int32_t chunk_req = 0) {
+    std::memset(&L, 0, sizeof L);
+    if (!s || n_sys < 1) return false;
+    const size_t cap = far_capacity(s, n_sys);
+    h.sys.assign(n_sys, SysInfo{});
+    h.pairs.assign(cap, FarPair{0, 0});
+    h.keys.assign(cap, 0);
+    h.ft = FarTmp{h.pairs.data(), h.keys.data(), cap};
+    return make_layout(s, n_sys, m_max, L, h.sys.data(), h.ft, cfg_req, chunk_req);
 }
 
 static double* trace_buffer(const ff_ctx* c) {
     return at<double>(c->ws, c->L.off_vec) + (size_t)V_COUNT * c->L.vstride;
 }
 
-// Host-side validation of one system; returns FF_OK or the error.
-static ff_status validate_system(const ff_system* s, int k, std::vector<uint64_t>& excl, int aoff) {
+// Host-side validation of one system; returns FF_OK or the error.  Sets the
+// near-exclusion bits of its atoms in excl (global padded index).
+static ff_status validate_system(const ff_system* s, int k, uint64_t* excl, int aoff) {
     const int n = s->n_atoms;
     if (!s->q || !s->sigma || !s->eps) return fail(FF_ERR_ARG, "system %d: per-atom parameter arrays are null", k);
     if ((s->n_bonds && (!s->bond || !s->bond_k || !s->bond_r0)) ||
@@ -286,19 +316,184 @@ static ff_status validate_system(const ff_system* s, int k, std::vector<uint64_t
     return FF_OK;
 }
 
-// ---------------------------------------------------------------- C ABI
+// Validates the systems and writes the host image of the workspace's packed
+// part, [0, L.static_end), into img: per-atom factors, exclusion bitmasks,
+// tile tables, bonded topology with the per-atom incidence lists, far
+// exclusion masks and the grid maps.  Uses no heap memory.
+static ff_status pack_static(const ff_system* systems, int32_t n_sys, const Layout& L, const SysInfo* sys,
+                             const FarTmp& ft, char* img) {
+    std::memset(img, 0, L.static_end);
+    uint64_t* excl = at<uint64_t>(img, L.off_excl);
+    for (int k = 0; k < n_sys; ++k) {
+        ff_status st = validate_system(&systems[k], k, excl, sys[k].aoff);
+        if (st) return st;
+    }
+    std::memcpy(img + L.off_sys, sys, (size_t)n_sys * sizeof(SysInfo));
+    // per-atom factors: c12 = 2 sqrt(eps) sigma^6, c6 = 2 sqrt(eps) sigma^3,
+    // q^ = sqrt(C) q; padding atoms keep zero factors
+    float* c12f = at<float>(img, L.off_c12);
+    float* c6f = at<float>(img, L.off_c6);
+    float* qf = at<float>(img, L.off_q);
+    double* c12d = at<double>(img, L.off_c12d);
+    double* c6d = at<double>(img, L.off_c6d);
+    double* qd = at<double>(img, L.off_qd);
+    for (int k = 0; k < n_sys; ++k) {
+        const ff_system& s = systems[k];
+        const double sqc = std::sqrt(s.coulomb_c);
+        for (int i = 0; i < s.n_atoms; ++i) {
+            const int g = sys[k].aoff + i;
+            const double se = 2.0 * std::sqrt(s.eps[i]);
+            const double s3 = s.sigma[i] * s.sigma[i] * s.sigma[i];
+            c12d[g] = se * s3 * s3;
+            c6d[g] = se * s3;
+            qd[g] = sqc * s.q[i];
+            c12f[g] = (float)c12d[g];
+            c6f[g] = (float)c6d[g];
+            qf[g] = (float)qd[g];
+        }
+    }
+    // tile tables (global I-block and j-tile indices)
+    ChunkInfo* chunks = at<ChunkInfo>(img, L.off_chunks);
+    RowInfo* rows = at<RowInfo>(img, L.off_rows);
+    int unit = 0, nch = 0;
+    for (int k = 0; k < n_sys; ++k) {
+        const SysInfo& si = sys[k];
+        const int tile0 = si.aoff / kTile, nt = si.np / kTile;
+        for (int b = 0; b < si.nb; ++b) {
+            const int row = si.row0 + b;
+            const int t0 = tile0 + b * L.block / kTile, t_end = tile0 + nt;
+            rows[row].unit_start = unit;
+            rows[row].t0 = t0;
+            rows[row].chunk_start = nch;
+            for (int t = t0; t < t_end; t += L.chunk) {
+                ChunkInfo& c = chunks[nch++];
+                c.row = row;
+                c.t_begin = t;
+                c.t_end = std::min(t + L.chunk, t_end);
+                c.unit_base = unit + (t - t0);
+                c.sys = k;
+            }
+            rows[row].n_chunks = nch - rows[row].chunk_start;
+            unit += t_end - t0;
+        }
+    }
+    if (nch != L.n_chunks || unit != L.n_units) return fail(FF_ERR_ARG, "internal: tile table size mismatch");
+    // bonded topology (local atom indices) and parameters
+    int* bond = at<int>(img, L.off_bond);
+    double* bondp = at<double>(img, L.off_bondp);
+    int* angle = at<int>(img, L.off_angle);
+    double* anglep = at<double>(img, L.off_anglep);
+    int* dih = at<int>(img, L.off_dih);
+    double* dihp = at<double>(img, L.off_dihp);
+    const int abase = 2 * L.n_bonds, dbase = abase + 3 * L.n_angles;
+    for (int k = 0; k < n_sys; ++k) {
+        const ff_system& s = systems[k];
+        const SysInfo& si = sys[k];
+        for (int b = 0; b < s.n_bonds; ++b) {
+            const int gb = si.bond0 + b;
+            bond[2 * gb] = s.bond[2 * b];
+            bond[2 * gb + 1] = s.bond[2 * b + 1];
+            bondp[2 * gb] = s.bond_k[b];
+            bondp[2 * gb + 1] = s.bond_r0[b];
+        }
+        for (int a = 0; a < s.n_angles; ++a) {
+            const int ga = si.angle0 + a;
+            for (int q = 0; q < 3; ++q) angle[3 * ga + q] = s.angle[3 * a + q];
+            anglep[2 * ga] = s.angle_k[a];
+            anglep[2 * ga + 1] = s.angle_t0[a];
+        }
+        for (int d = 0; d < s.n_dihedrals; ++d) {
+            const int gd = si.dih0 + d;
+            for (int q = 0; q < 4; ++q) {
+                dih[4 * gd + q] = s.dihedral[4 * d + q];
+                dihp[4 * gd + q] = s.dihedral_v[4 * d + q];
+            }
+        }
+    }
+    // incidence lists: the term slots of every global padded atom in
+    // increasing slot order (bonds, then angles, then torsions), by counting;
+    // inc_start[a + 1] serves as atom a's fill cursor and ends at the start of
+    // atom a + 1
+    int* inc_start = at<int>(img, L.off_inc_start);
+    int* inc = at<int>(img, L.off_inc);
+    auto each_slot = [&](auto&& visit) {
+        for (int k = 0; k < n_sys; ++k) {
+            const ff_system& s = systems[k];
+            const SysInfo& si = sys[k];
+            for (int b = 0; b < s.n_bonds; ++b)
+                for (int q = 0; q < 2; ++q) visit(si.aoff + s.bond[2 * b + q], 2 * (si.bond0 + b) + q);
+            for (int a = 0; a < s.n_angles; ++a)
+                for (int q = 0; q < 3; ++q) visit(si.aoff + s.angle[3 * a + q], abase + 3 * (si.angle0 + a) + q);
+            for (int d = 0; d < s.n_dihedrals; ++d)
+                for (int q = 0; q < 4; ++q) visit(si.aoff + s.dihedral[4 * d + q], dbase + 4 * (si.dih0 + d) + q);
+        }
+    };
+    // (counts of atom a at a + 2: after the prefix sum inc_start[a + 1] is
+    // where atom a's list starts; the last atom's count is not needed)
+    each_slot([&](int atom, int) { if (atom + 2 <= L.np) ++inc_start[atom + 2]; });
+    for (int a = 2; a <= L.np; ++a) inc_start[a] += inc_start[a - 1];
+    each_slot([&](int atom, int slot) { inc[inc_start[atom + 1]++] = slot; });
+    if (inc_start[L.np] != L.n_terms_slots) return fail(FF_ERR_ARG, "internal: incidence list size mismatch");
+    // far exclusions: per-unit index of its mask block, or -1, and per
+    // (unit, i-atom) masks over the unit's j-tile
+    int32_t* fu = at<int32_t>(img, L.off_far_unit);
+    uint64_t* fm = at<uint64_t>(img, L.off_far_mask);
+    for (int u = 0; u < L.n_units; ++u) fu[u] = -1;
+    for (size_t q = 0; q < ft.n_keys; ++q) {
+        const int row = (int)(ft.keys[q] >> 32), t = (int)(ft.keys[q] & 0xffffffffLL);
+        fu[rows[row].unit_start + t - rows[row].t0] = (int32_t)q;
+    }
+    for (size_t q = 0; q < ft.n_pairs; ++q) {
+        const FarPair& p = ft.pairs[q];
+        const int row = p.lo / L.block, t = p.hi / kTile;
+        const int blk = fu[rows[row].unit_start + t - rows[row].t0];
+        fm[(size_t)blk * L.block + (p.lo - row * L.block)] |= 1ull << (p.hi - t * kTile);
+    }
+    // flat grid maps: (system, local block) of every workgroup
+    int32_t* mf = at<int32_t>(img, L.off_map_fin);
+    int32_t* mv = at<int32_t>(img, L.off_map_vec);
+    int32_t* mb = at<int32_t>(img, L.off_map_bonded);
+    int32_t* ma = at<int32_t>(img, L.off_map_acc);
+    for (int k = 0; k < n_sys; ++k) {
+        for (int b = 0; b < sys[k].fin_blocks; ++b) { *mf++ = k; *mf++ = b; }
+        for (int b = 0; b < sys[k].vec_blocks; ++b) { *mv++ = k; *mv++ = b; }
+        for (int b = 0; b < sys[k].bonded_blocks; ++b) { *mb++ = k; *mb++ = b; }
+        for (int b = 0; b < sys[k].acc_bx; ++b) { *ma++ = k; *ma++ = b; }
+    }
+    return FF_OK;
+}
+
+// Bonded terms, pair kernel and finalize of one direct evaluation.
+static ff_status launch_energy(const Layout& L, char* ws, const double* xyz, double* energy, double* grad,
+                               int32_t precision, hipStream_t st) {
+    Args a{};
+    a.L = L;
+    a.ws = ws;
+    a.xyz_in = xyz;
+    a.e_out = energy;
+    a.g_out = grad;
+    a.direct = 1;
+    a.direct_prec = precision;
+    HIP_TRY(launch_bonded(a, st));
+    HIP_TRY(launch_pair(a, precision, st));
+    HIP_TRY(launch_finalize(a, st));
+    return FF_OK;
+}
+
 extern "C" {
 
 size_t ff_workspace_bytes_batch(const ff_system* sys, int32_t n_sys, int32_t m_max) {
     Layout L;
-    if (!make_layout(sys, n_sys, m_max, L, nullptr)) return 0;
+    LayoutHost h;
+    if (!layout_heap(sys, n_sys, m_max, L, h)) return 0;
     return L.total;
 }
 
 size_t ff_workspace_bytes_tiled(const ff_system* sys, int32_t n_sys, int32_t m_max, int32_t tile_config,
                                 int32_t chunk) {
     Layout L;
-    if (tile_config < 0 || !make_layout(sys, n_sys, m_max, L, nullptr, tile_config, chunk)) return 0;
+    LayoutHost h;
+    if (tile_config < 0 || !layout_heap(sys, n_sys, m_max, L, h, tile_config, chunk)) return 0;
     return L.total;
 }
 
@@ -306,7 +501,7 @@ int32_t ff_num_tile_configs(void) { return kNumTileConfigs; }
 
 ff_status ff_tile_config_info(int32_t cfg, int32_t* block, int32_t* waves32, int32_t* ipl32, int32_t* waves64,
                               int32_t* ipl64) {
-    g_err.clear();
+    clear_error();
     if (cfg < 0 || cfg >= kNumTileConfigs) return fail(FF_ERR_ARG, "tile configuration %d outside [0, %d)", cfg,
                                                        kNumTileConfigs);
     const TileConfig& t = kTileConfigs[cfg];
@@ -342,13 +537,13 @@ void ff_default_params(ff_min_params* p) {
     p->hb_beta = 0.0;
 }
 
-const char* ff_last_error(void) { return g_err.c_str(); }
+const char* ff_last_error(void) { return g_err; }
 
 int32_t ff_batch_size(const ff_ctx* c) { return c ? c->L.n_sys : 0; }
 
 static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes,
                              int32_t m_max, int32_t cfg_req, int32_t chunk_req, void* stream, ff_ctx** out) {
-    g_err.clear();
+    clear_error();
     if (!out) return fail(FF_ERR_ARG, "out is null");
     *out = nullptr;
     if (!systems || n_sys < 1) return fail(FF_ERR_ARG, "need at least one system");
@@ -356,164 +551,19 @@ static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* work
         if (systems[k].n_atoms < 1) return fail(FF_ERR_ARG, "system %d: n_atoms must be >= 1", k);
     if (m_max < 0 || m_max > kMaxM) return fail(FF_ERR_ARG, "m_max must be in [0, %d]", kMaxM);
     Layout L;
-    std::vector<SysInfo> sys;
+    LayoutHost h;
     if (cfg_req >= 0 && (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk))
         return fail(FF_ERR_ARG, "tile configuration %d / chunk %d outside [0, %d) / [1, %d]", cfg_req, chunk_req,
                     kNumTileConfigs, kMaxChunk);
-    if (!make_layout(systems, n_sys, m_max, L, &sys, cfg_req, chunk_req)) return fail(FF_ERR_ARG, "invalid sizes");
+    if (!layout_heap(systems, n_sys, m_max, L, h, cfg_req, chunk_req)) return fail(FF_ERR_ARG, "invalid sizes");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(FF_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
     if (ws_bytes < L.total) return fail(FF_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
-    std::vector<uint64_t> excl(L.np, 0ull);
-    for (int k = 0; k < n_sys; ++k) {
-        ff_status st = validate_system(&systems[k], k, excl, sys[k].aoff);
-        if (st) return st;
-    }
-    // per-atom factors: c12 = 2 sqrt(eps) sigma^6, c6 = 2 sqrt(eps) sigma^3, q^ = sqrt(C) q;
-    // padding atoms keep zero factors
-    std::vector<float> c12f(L.np, 0.f), c6f(L.np, 0.f), qf(L.np, 0.f);
-    std::vector<double> c12d(L.np, 0.0), c6d(L.np, 0.0), qd(L.np, 0.0);
-    for (int k = 0; k < n_sys; ++k) {
-        const ff_system& s = systems[k];
-        const double sqc = std::sqrt(s.coulomb_c);
-        for (int i = 0; i < s.n_atoms; ++i) {
-            const int g = sys[k].aoff + i;
-            const double se = 2.0 * std::sqrt(s.eps[i]);
-            const double s3 = s.sigma[i] * s.sigma[i] * s.sigma[i];
-            c12d[g] = se * s3 * s3;
-            c6d[g] = se * s3;
-            qd[g] = sqc * s.q[i];
-            c12f[g] = (float)c12d[g];
-            c6f[g] = (float)c6d[g];
-            qf[g] = (float)qd[g];
-        }
-    }
-    // tile tables (global I-block and j-tile indices)
-    std::vector<ChunkInfo> chunks;
-    std::vector<RowInfo> rows(L.nb);
-    int unit = 0;
-    for (int k = 0; k < n_sys; ++k) {
-        const SysInfo& si = sys[k];
-        const int tile0 = si.aoff / kTile, nt = si.np / kTile;
-        for (int b = 0; b < si.nb; ++b) {
-            const int row = si.row0 + b;
-            const int t0 = tile0 + b * L.block / kTile, t_end = tile0 + nt;
-            rows[row].unit_start = unit;
-            rows[row].t0 = t0;
-            rows[row].chunk_start = (int)chunks.size();
-            for (int t = t0; t < t_end; t += L.chunk) {
-                ChunkInfo c{};
-                c.row = row;
-                c.t_begin = t;
-                c.t_end = std::min(t + L.chunk, t_end);
-                c.unit_base = unit + (t - t0);
-                c.sys = k;
-                chunks.push_back(c);
-            }
-            rows[row].n_chunks = (int)chunks.size() - rows[row].chunk_start;
-            unit += t_end - t0;
-        }
-    }
-    // bonded topology (local atom indices) and the incidence lists (global
-    // term-slot indices per global padded atom)
-    std::vector<int> bond(2 * (size_t)L.n_bonds), angle(3 * (size_t)L.n_angles), dih(4 * (size_t)L.n_dihedrals);
-    std::vector<double> bondp(2 * (size_t)L.n_bonds), anglep(2 * (size_t)L.n_angles), dihp(4 * (size_t)L.n_dihedrals);
-    std::vector<std::vector<int>> inc_lists(L.np);
-    const int abase = 2 * L.n_bonds, dbase = abase + 3 * L.n_angles;
-    for (int k = 0; k < n_sys; ++k) {
-        const ff_system& s = systems[k];
-        const SysInfo& si = sys[k];
-        for (int b = 0; b < s.n_bonds; ++b) {
-            const int gb = si.bond0 + b;
-            for (int q = 0; q < 2; ++q) {
-                bond[2 * gb + q] = s.bond[2 * b + q];
-                inc_lists[si.aoff + s.bond[2 * b + q]].push_back(2 * gb + q);
-            }
-            bondp[2 * gb] = s.bond_k[b];
-            bondp[2 * gb + 1] = s.bond_r0[b];
-        }
-        for (int a = 0; a < s.n_angles; ++a) {
-            const int ga = si.angle0 + a;
-            for (int q = 0; q < 3; ++q) {
-                angle[3 * ga + q] = s.angle[3 * a + q];
-                inc_lists[si.aoff + s.angle[3 * a + q]].push_back(abase + 3 * ga + q);
-            }
-            anglep[2 * ga] = s.angle_k[a];
-            anglep[2 * ga + 1] = s.angle_t0[a];
-        }
-        for (int d = 0; d < s.n_dihedrals; ++d) {
-            const int gd = si.dih0 + d;
-            for (int q = 0; q < 4; ++q) {
-                dih[4 * gd + q] = s.dihedral[4 * d + q];
-                dihp[4 * gd + q] = s.dihedral_v[4 * d + q];
-                inc_lists[si.aoff + s.dihedral[4 * d + q]].push_back(dbase + 4 * gd + q);
-            }
-        }
-    }
-    std::vector<int> inc_start(L.np + 1, 0), inc;
-    inc.reserve(L.n_terms_slots);
-    for (int i = 0; i < L.np; ++i) {
-        inc_start[i] = (int)inc.size();
-        for (int v : inc_lists[i]) inc.push_back(v);
-    }
-    inc_start[L.np] = (int)inc.size();
-
+    std::vector<char> img(L.static_end);
+    ff_status ps = pack_static(systems, n_sys, L, h.sys.data(), h.ft, img.data());
+    if (ps) return ps;
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
-    auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
-        if (!bytes) return hipSuccess;
-        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
-    };
-    HIP_TRY(up(L.off_sys, sys.data(), sys.size() * sizeof(SysInfo)));
-    HIP_TRY(up(L.off_c12, c12f.data(), c12f.size() * 4));
-    HIP_TRY(up(L.off_c6, c6f.data(), c6f.size() * 4));
-    HIP_TRY(up(L.off_q, qf.data(), qf.size() * 4));
-    HIP_TRY(up(L.off_c12d, c12d.data(), c12d.size() * 8));
-    HIP_TRY(up(L.off_c6d, c6d.data(), c6d.size() * 8));
-    HIP_TRY(up(L.off_qd, qd.data(), qd.size() * 8));
-    HIP_TRY(up(L.off_excl, excl.data(), excl.size() * 8));
-    HIP_TRY(up(L.off_chunks, chunks.data(), chunks.size() * sizeof(ChunkInfo)));
-    HIP_TRY(up(L.off_rows, rows.data(), rows.size() * sizeof(RowInfo)));
-    HIP_TRY(up(L.off_bond, bond.data(), bond.size() * 4));
-    HIP_TRY(up(L.off_bondp, bondp.data(), bondp.size() * 8));
-    HIP_TRY(up(L.off_angle, angle.data(), angle.size() * 4));
-    HIP_TRY(up(L.off_anglep, anglep.data(), anglep.size() * 8));
-    HIP_TRY(up(L.off_dih, dih.data(), dih.size() * 4));
-    HIP_TRY(up(L.off_dihp, dihp.data(), dihp.size() * 8));
-    HIP_TRY(up(L.off_inc_start, inc_start.data(), inc_start.size() * 4));
-    HIP_TRY(up(L.off_inc, inc.data(), inc.size() * 4));
-    // far exclusions: per-unit index and per-(unit, i-atom) masks over the j-tile
-    {
-        std::vector<std::pair<int, int>> far;
-        for (int k = 0; k < n_sys; ++k) far_exclusions(systems[k], sys[k].aoff, far);
-        const std::vector<long long> keys = far_unit_keys(far, L.block);
-        std::vector<int32_t> fu(L.n_units, -1);
-        std::vector<uint64_t> fm((size_t)keys.size() * L.block, 0ull);
-        for (size_t q = 0; q < keys.size(); ++q) {
-            const int row = (int)(keys[q] >> 32), t = (int)(keys[q] & 0xffffffffLL);
-            fu[rows[row].unit_start + t - rows[row].t0] = (int32_t)q;
-        }
-        for (auto& p : far) {
-            const int row = p.first / L.block, t = p.second / kTile;
-            const int q = fu[rows[row].unit_start + t - rows[row].t0];
-            fm[(size_t)q * L.block + (p.first - row * L.block)] |= 1ull << (p.second - t * kTile);
-        }
-        HIP_TRY(up(L.off_far_unit, fu.data(), fu.size() * 4));
-        if (!fm.empty()) HIP_TRY(up(L.off_far_mask, fm.data(), fm.size() * 8));
-    }
-    // flat grid maps: (system, local block) of every workgroup
-    {
-        std::vector<int32_t> mf, mv, mb, ma;
-        for (int k = 0; k < n_sys; ++k) {
-            for (int b = 0; b < sys[k].fin_blocks; ++b) { mf.push_back(k); mf.push_back(b); }
-            for (int b = 0; b < sys[k].vec_blocks; ++b) { mv.push_back(k); mv.push_back(b); }
-            for (int b = 0; b < sys[k].bonded_blocks; ++b) { mb.push_back(k); mb.push_back(b); }
-            for (int b = 0; b < sys[k].acc_bx; ++b) { ma.push_back(k); ma.push_back(b); }
-        }
-        HIP_TRY(up(L.off_map_fin, mf.data(), mf.size() * 4));
-        HIP_TRY(up(L.off_map_vec, mv.data(), mv.size() * 4));
-        HIP_TRY(up(L.off_map_bonded, mb.data(), mb.size() * 4));
-        HIP_TRY(up(L.off_map_acc, ma.data(), ma.size() * 4));
-    }
+    HIP_TRY(hipMemcpyAsync(ws, img.data(), L.static_end, hipMemcpyHostToDevice, st));
     Args a{};
     a.L = L;
     a.ws = ws;
@@ -523,7 +573,7 @@ static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* work
     ff_ctx* c = new ff_ctx();
     c->L = L;
     c->ws = ws;
-    c->sys = std::move(sys);
+    c->sys = std::move(h.sys);
     void* hf = nullptr;
     void* hc = nullptr;
     if (hipHostMalloc(&hf, 256, hipHostMallocDefault) != hipSuccess ||
@@ -552,7 +602,7 @@ ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspa
 ff_status ff_create_tiled(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes,
                           int32_t m_max, int32_t tile_config, int32_t chunk, void* stream, ff_ctx** out) {
     if (tile_config < 0) {
-        g_err = "tile_config must be >= 0 (ff_create_batch picks one itself)";
+        fail(FF_ERR_ARG, "tile_config must be >= 0 (ff_create_batch picks one itself)");
         if (out) *out = nullptr;
         return FF_ERR_ARG;
     }
@@ -561,7 +611,7 @@ ff_status ff_create_tiled(const ff_system* systems, int32_t n_sys, void* workspa
 
 ff_status ff_get_tiling(const ff_ctx* c, int32_t* tile_config, int32_t* chunk) {
     if (!c) {
-        g_err = "context is null";
+        fail(FF_ERR_ARG, "context is null");
         return FF_ERR_ARG;
     }
     if (tile_config) *tile_config = c->L.cfg;
@@ -577,7 +627,8 @@ size_t ff_autotune_workspace_bytes(const ff_system* systems, int32_t n_sys) {
     for (int cfg = 0; cfg < kNumTileConfigs; ++cfg)
         for (int32_t ch : kTuneChunks) {
             Layout L;
-            if (!make_layout(systems, n_sys, 0, L, nullptr, cfg, ch)) return 0;
+            LayoutHost h;
+            if (!layout_heap(systems, n_sys, 0, L, h, cfg, ch)) return 0;
             best = std::max(best, L.total);
         }
     return best ? best + align256(8 * (size_t)n_sys) : 0;
@@ -586,7 +637,7 @@ size_t ff_autotune_workspace_bytes(const ff_system* systems, int32_t n_sys) {
 ff_status ff_autotune(const ff_system* systems, int32_t n_sys, const double* xyz, void* workspace,
                       size_t ws_bytes, int32_t precision, int32_t reps, void* stream, int32_t* tile_config,
                       int32_t* chunk, double* ms_per_eval) {
-    g_err.clear();
+    clear_error();
     if (!systems || n_sys < 1 || !xyz || !workspace || reps < 1 || !tile_config || !chunk)
         return fail(FF_ERR_ARG, "bad arguments");
     if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
@@ -607,7 +658,8 @@ ff_status ff_autotune(const ff_system* systems, int32_t n_sys, const double* xyz
     for (int cfg = 0; cfg < kNumTileConfigs && result == FF_OK; ++cfg) {
         for (int32_t ch : kTuneChunks) {
             Layout L;
-            if (!make_layout(systems, n_sys, 0, L, nullptr, cfg, ch) || L.total > usable) continue;
+            LayoutHost h;
+            if (!layout_heap(systems, n_sys, 0, L, h, cfg, ch) || L.total > usable) continue;
             ff_ctx* c = nullptr;
             ff_status s = create_impl(systems, n_sys, workspace, usable, 0, cfg, ch, stream, &c);
             if (s) { result = s; break; }
@@ -639,7 +691,7 @@ ff_status ff_autotune(const ff_system* systems, int32_t n_sys, const double* xyz
 ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_t m_max, void* stream,
                     ff_ctx** out) {
     if (!s) {
-        g_err = "system is null";
+        fail(FF_ERR_ARG, "system is null");
         if (out) *out = nullptr;
         return FF_ERR_ARG;
     }
@@ -658,23 +710,11 @@ ff_status ff_destroy(ff_ctx* c) {
 
 ff_status ff_energy_grad(ff_ctx* c, const double* xyz, double* energy, double* grad, int32_t precision,
                          void* stream) {
-    g_err.clear();
+    clear_error();
     if (!c) return fail(FF_ERR_ARG, "context is null");
     if (!xyz || !energy) return fail(FF_ERR_ARG, "xyz and energy must be device pointers");
     if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
-    hipStream_t st = (hipStream_t)stream;
-    Args a{};
-    a.L = c->L;
-    a.ws = c->ws;
-    a.xyz_in = xyz;
-    a.e_out = energy;
-    a.g_out = grad;
-    a.direct = 1;
-    a.direct_prec = precision;
-    HIP_TRY(launch_bonded(a, st));
-    HIP_TRY(launch_pair(a, precision, st));
-    HIP_TRY(launch_finalize(a, st));
-    return FF_OK;
+    return launch_energy(c->L, c->ws, xyz, energy, grad, precision, (hipStream_t)stream);
 }
 
 static constexpr int kCyclesPerGraph = 4;
@@ -706,7 +746,7 @@ static ff_status build_graph(ff_ctx* c) {
 }
 
 ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_result* res, void* stream) {
-    g_err.clear();
+    clear_error();
     if (!c || !xyz || !p || !res) return fail(FF_ERR_ARG, "null argument");
     if (p->method < FF_GD || p->method > FF_OGM) return fail(FF_ERR_ARG, "bad method %d", p->method);
     if (p->method == FF_HB && !(p->hb_alpha > 0.0 && std::isfinite(p->hb_alpha) && p->hb_beta >= 0.0 &&
@@ -805,11 +845,11 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     return FF_OK;
 }
 
-// Average duration (ms) of `reps` back-to-back launches of the pair kernel
-// alone at xyz (all systems), timed with HIP events recorded on the launch stream.
+// Energy along the unit antigradient of each system at xyz (section 3's
+// non-convexity profile): one evaluation at xyz, then one per step length.
 ff_status ff_energy_profile(ff_ctx* c, const double* xyz, const double* t, int32_t n_t, double* e_out,
                             int32_t precision, void* stream) {
-    g_err.clear();
+    clear_error();
     if (!c || !xyz || !t || !e_out) return fail(FF_ERR_ARG, "null argument");
     if (n_t < 1 || n_t > kMaxProfile) return fail(FF_ERR_ARG, "n_t must be in [1, %d]", kMaxProfile);
     if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
@@ -853,9 +893,11 @@ ff_status ff_energy_profile(ff_ctx* c, const double* xyz, const double* t, int32
     return FF_OK;
 }
 
+// Average duration (ms) of `reps` back-to-back launches of the pair kernel
+// alone at xyz (all systems), timed with HIP events recorded on the launch stream.
 ff_status ff_time_pair(ff_ctx* c, const double* xyz, int32_t precision, int32_t reps, void* stream,
                        double* avg_ms) {
-    g_err.clear();
+    clear_error();
     if (!c || !xyz || !avg_ms || reps < 1) return fail(FF_ERR_ARG, "bad arguments");
     if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision");
     hipStream_t st = stream ? (hipStream_t)stream : c->own;

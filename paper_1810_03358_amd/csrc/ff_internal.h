@@ -2,9 +2,10 @@
 //
 // A context holds a batch of one or more independent systems.  Workspace
 // (caller-allocated device memory) =
-//   [batch counters | per-system info | per-system control blocks |
-//    packed parameters | topology | tile tables | pair partials |
-//    bonded partials | reduction partials | FP64 vectors]
+//   [per-system info | packed parameters | tile tables | topology |
+//    grid maps | far-exclusion masks]   (packed once, read only)
+//   [batch counters | per-system control blocks | pair partials |
+//    bonded partials | reduction partials | FP64 vectors]   (kernel state)
 // Every region starts on a 256-byte boundary.  Systems are concatenated: each
 // is padded to a multiple of the I-block size and occupies a contiguous range
 // of padded atoms (and 3x that range in every FP64 vector).
@@ -221,6 +222,7 @@ struct Layout {
     size_t off_map_fin, off_map_vec, off_map_bonded, off_map_acc;   // int2 maps of the flat grids
     size_t off_far_unit;      // int32 per unit: its far-mask block, or -1
     size_t off_far_mask;      // uint64 [n_far_units][block]: bit jl = pair (i, tile atom jl) excluded
+    size_t static_end;        // [0, static_end): the packed regions, written once per context
     size_t total;
 };
 

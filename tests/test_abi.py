@@ -207,3 +207,21 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_output_buffers_are_checked_before_any_kernel_writes_them():
+    import torch
+    from paper_1810_03358_amd import _out_tensor
+    x = torch.zeros(30, dtype=torch.float64)      # stands in for checked coordinates
+    with pytest.raises(ValueError, match="float64"):
+        _out_tensor(torch.zeros(30, dtype=torch.float32), 30, x, "out_g")
+    with pytest.raises(ValueError, match="elements"):
+        _out_tensor(torch.zeros(0, dtype=torch.float64), 1, x, "out_e")
+    with pytest.raises(ValueError, match="elements"):
+        _out_tensor(torch.zeros(29, dtype=torch.float64), 30, x, "out_g")
+    with pytest.raises(ValueError, match="contiguous"):
+        _out_tensor(torch.zeros(60, dtype=torch.float64)[::2], 30, x, "out_g")
+    with pytest.raises(ValueError, match="on meta"):
+        _out_tensor(torch.zeros(30, dtype=torch.float64, device="meta"), 30, x, "out_g")
+    t = torch.zeros(30, dtype=torch.float64)
+    assert _out_tensor(t, 30, x, "out_g") is t
