@@ -219,6 +219,31 @@ ff_status ff_destroy(ff_ctx *ctx);
 ff_status ff_energy_grad(ff_ctx *ctx, const double *xyz, double *energy, double *grad,
                          int32_t precision, void *stream);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): ff_energy_grad of ONE system with neither
+ * a context nor a caller workspace.  The library keeps a static device array
+ * of FF_NOALLOC_SCRATCH_BYTES on every GPU it runs on (held until the process
+ * ends) and packs the system into it on every call: the same packing, tiling
+ * and kernels as ff_create followed by ff_energy_grad, hence the same results.
+ *  - sys: host struct as for ff_create; xyz [n_atoms][3], energy [1] and grad
+ *    [n_atoms][3] (or NULL): device pointers; precision: ff_precision.
+ *  - Blocks until the packed system has been copied to the device (the copy
+ *    is ordered after earlier work on `stream`), then enqueues the evaluation
+ *    on `stream` and returns.  Not for HIP graph capture (it copies from host
+ *    memory and waits for that copy).
+ *  - Allocates nothing: no hipMalloc / hipHostMalloc, no stream, event or
+ *    graph creation, no heap memory.
+ *  - All calls on one GPU share that GPU's array, which keeps the last call's
+ *    contents: calls on one stream are ordered, but a call whose evaluation
+ *    can overlap another call's on the same GPU (other streams, other
+ *    threads) races with it.
+ *  - A system whose workspace exceeds FF_NOALLOC_SCRATCH_BYTES (chains of up
+ *    to about 20,000 atoms fit) gives FF_ERR_UNSUPPORTED before any device
+ *    work; other errors as for ff_create and ff_energy_grad. */
+#define FF_NOALLOC_SCRATCH_BYTES (64u << 20)
+ff_status ff_energy_grad_noalloc(const ff_system *sys, const double *xyz, double *energy, double *grad,
+                                 int32_t precision, void *stream);
+
 /* Local minimization from xyz_inout (device, concatenated [n][3]); on return
  * it holds the result points: the last iterate for GD, CG, L-BFGS, heavy ball
  * and OGM, the best iterate for FGM (Algorithm 1).  result: host array of n_sys entries.

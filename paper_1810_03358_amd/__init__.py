@@ -123,6 +123,27 @@ def _out_tensor(t, numel: int, x: torch.Tensor, name: str) -> torch.Tensor:
     return t
 
 
+def energy_grad_noalloc(system: dict, x: torch.Tensor, out_e: torch.Tensor, out_g: torch.Tensor | None = None,
+                        precision: str | int = "fp64", stream=None):
+    """E and grad E of one system at x through ff_energy_grad_noalloc: no
+    context, no workspace; the library's static device scratch instead.  The
+    caller passes the outputs (out_e: >= 1 float64 entry, out_g: like x or
+    None).  Blocks until the packed system is on the device, then returns with
+    the evaluation enqueued on the stream."""
+    hs = HostSystem(system)
+    if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()
+            and x.numel() == 3 * hs.n):
+        raise ValueError("coordinates must be a contiguous float64 CUDA tensor with 3*n_atoms elements")
+    _out_tensor(out_e, 1, x, "out_e")
+    if out_g is not None:
+        _out_tensor(out_g, x.numel(), x, "out_g")
+    _check(N.load().ff_energy_grad_noalloc(C.byref(hs.c), C.c_void_p(x.data_ptr()), C.c_void_p(out_e.data_ptr()),
+                                           C.c_void_p(out_g.data_ptr()) if out_g is not None else None,
+                                           int(PRECISIONS.get(precision, precision)), _stream_ptr(stream)),
+           "ff_energy_grad_noalloc")
+    return out_e, out_g
+
+
 class Context:
     """Prepared system(s) on one GPU: workspace (torch uint8 tensor) + ff_ctx.
 

@@ -15,6 +15,7 @@ FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START, FF_DIVERGED = 0, 1,
 FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H = -1, 0, 1
 FF_MIN_RESUME, FF_MIN_NO_CERTIFY = 1, 2
 FF_CG_PRP, FF_CG_FR, FF_CG_HS, FF_CG_PRP_PLUS, FF_CG_CD, FF_CG_LS, FF_CG_DY = 0, 1, 2, 3, 4, 5, 6
+FF_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -50,7 +51,8 @@ class FFMinResult(C.Structure):
 EXPORTS = ("ff_workspace_bytes", "ff_workspace_bytes_batch", "ff_create", "ff_create_batch", "ff_batch_size",
            "ff_destroy", "ff_energy_grad", "ff_minimize", "ff_get_trace", "ff_time_pair", "ff_default_params",
            "ff_last_error", "ff_num_tile_configs", "ff_tile_config_info", "ff_workspace_bytes_tiled",
-           "ff_create_tiled", "ff_get_tiling", "ff_autotune_workspace_bytes", "ff_autotune", "ff_energy_profile")
+           "ff_create_tiled", "ff_get_tiling", "ff_autotune_workspace_bytes", "ff_autotune", "ff_energy_profile",
+           "ff_energy_grad_noalloc")
 
 LEARN_EXPORTS = ("ff_learn_param_count", "ff_learn_workspace_bytes", "ff_learn_last_error", "ff_learn_features",
                  "ff_learn_gemm", "ff_learn_forward", "ff_learn_backward", "ff_learn_adam", "ff_learn_to_bf16",
@@ -84,6 +86,9 @@ def load():
     lib.ff_destroy.restype = C.c_int
     lib.ff_energy_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
     lib.ff_energy_grad.restype = C.c_int
+    lib.ff_energy_grad_noalloc.argtypes = [C.POINTER(FFSystem), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                           C.c_void_p]
+    lib.ff_energy_grad_noalloc.restype = C.c_int
     lib.ff_minimize.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(FFMinParams), C.POINTER(FFMinResult),
                                 C.c_void_p]
     lib.ff_minimize.restype = C.c_int

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ff.h"
@@ -69,6 +70,20 @@ static ff_status fail(ff_status st, const char* fmt, ...) {
     } while (0)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------- ff_energy_grad_noalloc
+// Device memory of ff_energy_grad_noalloc: a workspace laid out as for a
+// context of one system (without optimizer vectors), in a static array that
+// every GPU the library runs on holds until the process ends.  Host code never
+// uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_dev.
+static __device__ __align__(256) char scratch[FF_NOALLOC_SCRATCH_BYTES];
+// Host image of the packed regions (and the far-exclusion temporaries at its
+// end), rebuilt by every call.
+alignas(256) static char g_stage[FF_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices];
+static std::mutex g_noalloc_mu;      // guards g_stage and g_scratch_dev
 
 // ------------------------------------------------------------------ layout
 // An excluded pair (1-2 or 1-3) more than kExclWindow atoms apart, as global
@@ -249,7 +264,8 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     return true;
 }
 
-// make_layout with its host storage on the heap.
+// make_layout with its host storage on the heap (every entry point but
+// ff_energy_grad_noalloc).
 struct LayoutHost {
     std::vector<SysInfo> sys;
     std::vector<FarPair> pairs;
@@ -715,6 +731,52 @@ ff_status ff_energy_grad(ff_ctx* c, const double* xyz, double* energy, double* g
     if (!xyz || !energy) return fail(FF_ERR_ARG, "xyz and energy must be device pointers");
     if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
     return launch_energy(c->L, c->ws, xyz, energy, grad, precision, (hipStream_t)stream);
+}
+
+ff_status ff_energy_grad_noalloc(const ff_system* sys, const double* xyz, double* energy, double* grad,
+                                 int32_t precision, void* stream) {
+    clear_error();
+    if (!sys || !xyz || !energy) return fail(FF_ERR_ARG, "sys, xyz and energy must not be null");
+    if (sys->n_atoms < 1) return fail(FF_ERR_ARG, "n_atoms must be >= 1");
+    if (precision != FF_FP64 && precision != FF_FP32_ACC64) return fail(FF_ERR_ARG, "bad precision %d", precision);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    // the far-exclusion temporaries take the end of the host stage
+    const size_t cap = far_capacity(sys, 1);
+    const size_t tmp_bytes = align256(cap * (sizeof(FarPair) + sizeof(long long)));
+    if (tmp_bytes >= sizeof g_stage)
+        return fail(FF_ERR_UNSUPPORTED, "%zu bonds and angles exceed what ff_energy_grad_noalloc stages",
+                    (size_t)sys->n_bonds + (size_t)sys->n_angles);
+    char* tmp = g_stage + sizeof g_stage - tmp_bytes;
+    FarTmp ft{reinterpret_cast<FarPair*>(tmp), reinterpret_cast<long long*>(tmp + cap * sizeof(FarPair)), cap};
+    Layout L;
+    SysInfo si;
+    if (!make_layout(sys, 1, 0, L, &si, ft, -1, 0, true)) return fail(FF_ERR_ARG, "invalid sizes");
+    if (L.total > FF_NOALLOC_SCRATCH_BYTES || L.static_end > sizeof g_stage - tmp_bytes)
+        return fail(FF_ERR_UNSUPPORTED, "a system of %d atoms needs %zu bytes of device scratch; "
+                    "ff_energy_grad_noalloc has %zu (use a context)", sys->n_atoms, L.total,
+                    (size_t)FF_NOALLOC_SCRATCH_BYTES);
+    ff_status ps = pack_static(sys, 1, L, &si, ft, g_stage);
+    if (ps) return ps;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FF_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) return fail(FF_ERR_HIP, "scratch symbol address %p not usable", p);
+        g_scratch_dev[dev] = p;
+    }
+    char* ws = static_cast<char*>(g_scratch_dev[dev]);
+    hipStream_t st = (hipStream_t)stream;
+    // stream-ordered after earlier work on `stream`; the wait keeps the host
+    // stage intact until the copy has read it
+    HIP_TRY(hipMemcpyAsync(ws, g_stage, L.static_end, hipMemcpyHostToDevice, st));
+    Args a{};
+    a.L = L;
+    a.ws = ws;
+    HIP_TRY(launch_reset(a, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return launch_energy(L, ws, xyz, energy, grad, precision, st);
 }
 
 static constexpr int kCyclesPerGraph = 4;

@@ -225,3 +225,28 @@ def test_output_buffers_are_checked_before_any_kernel_writes_them():
         _out_tensor(torch.zeros(30, dtype=torch.float64, device="meta"), 30, x, "out_g")
     t = torch.zeros(30, dtype=torch.float64)
     assert _out_tensor(t, 30, x, "out_g") is t
+
+
+def _noalloc_status(system, precision=ff.FF_FP64):
+    hs = ff.HostSystem(system)
+    # any non-null pointers: every failure below is found before device work
+    return N.load().ff_energy_grad_noalloc(C.byref(hs.c), C.c_void_p(256), C.c_void_p(512), None, precision, None)
+
+
+def test_noalloc_rejects_oversized_and_bad_input_before_touching_the_device():
+    big = make_system(np_zeros(40_000))
+    assert _noalloc_status(big) == ff.FF_ERR_UNSUPPORTED
+    assert "scratch" in N.last_error() and str(N.FF_NOALLOC_SCRATCH_BYTES) in N.last_error()
+    good = chain_system(20, 1)
+    bad = dict(good, bonds=good["bonds"].copy())
+    bad["bonds"][3, 1] = 20
+    assert _noalloc_status(bad) == ff.FF_ERR_ARG and "bond 3" in N.last_error()
+    assert _noalloc_status(good, precision=7) == ff.FF_ERR_ARG
+    hs = ff.HostSystem(good)
+    assert N.load().ff_energy_grad_noalloc(C.byref(hs.c), None, C.c_void_p(512), None, 0, None) == ff.FF_ERR_ARG
+
+
+def test_noalloc_scratch_limit_matches_the_header():
+    text = open(os.path.join(INCLUDE, "ff.h")).read()
+    m = re.search(r"#define FF_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == N.FF_NOALLOC_SCRATCH_BYTES
