@@ -143,12 +143,12 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.n_sys = n_sys;
     // defaults from sweeps on MI355X: small systems and batches use 64-atom
     // blocks; large systems 256-atom blocks with two atoms per lane, and from
-    // 32768 atoms on also two per lane in the FP64 kernel (4 % faster at
-    // 50k atoms, 12 % slower at 10k)
+    // 32768 atoms on four per lane in the FP64 kernel (6 % faster than one
+    // at 50k atoms, 7 % slower at 10k)
     if (n_sys > 1) { L.cfg = 0; L.chunk = 4; }
     else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
     else if (n_max < 32768) { L.cfg = 4; L.chunk = 2; }
-    else { L.cfg = 7; L.chunk = 2; }
+    else { L.cfg = 8; L.chunk = 2; }
     if (cfg_req >= 0) {
         if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk) return false;
         L.cfg = cfg_req;

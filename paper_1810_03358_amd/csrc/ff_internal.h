@@ -164,6 +164,7 @@ constexpr TileConfig kTileConfigs[] = {
     {128, 2, 1, 2, 1},    // 5
     {128, 1, 2, 2, 1},    // 6
     {256, 2, 2, 2, 2},    // 7: as 4, with two atoms per lane in FP64 too
+    {256, 2, 2, 1, 4},    // 8: as 4, with four atoms per lane in FP64
 };
 constexpr int kNumTileConfigs = sizeof(kTileConfigs) / sizeof(kTileConfigs[0]);
 

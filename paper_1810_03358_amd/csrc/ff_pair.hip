@@ -19,11 +19,19 @@
 // Per pair, with per-atom factors prepared once per system
 //   c12 = 2 sqrt(eps) sigma^6,  c6 = 2 sqrt(eps) sigma^3,  q^ = sqrt(C) q
 // (so c12_i c12_j = 4 eps_ij sigma_ij^12, c6_i c6_j = 4 eps_ij sigma_ij^6,
-//  q^_i q^_j = C q_i q_j):
+//  q^_i q^_j = C q_i q_j), the terms of section 2 are
 //   e12 = c12_i c12_j / r^12, e6 = c6_i c6_j / r^6, ec = q^_i q^_j / r
 //   E  += e12 - e6 + ec
 //   f   = (12 e12 - 6 e6 + ec) / r^2,  d = x_j - x_i
-//   grad_i += f d,  grad_j -= f d
+//   grad_i += f d,  grad_j -= f d.
+// They are evaluated as follows, with the i-atom's factors held as 12 c12_i
+// and 6 c6_i (s = 1/r^6, A = 12 c12_i c12_j, B = 6 c6_i c6_j):
+//   u = A s - B                  (12 e12 - 6 e6 = u s)
+//   f = (u s + ec) / r^2
+//   L += (u - B) s               (12 e12 - 12 e6 = (u - B) s),  Ec += ec
+// and E = L / 12 + Ec: 13 operations after 1/r instead of 16 for the direct
+// form.  The Lennard-Jones and Coulomb sums are kept apart: one FP32 sum of
+// both (or of 12 E) loses about 1e-6 of |E| at relaxed 10^4-atom chains.
 #include "ff_internal.h"
 
 namespace ff {
@@ -203,7 +211,7 @@ __global__ void __launch_bounds__(kBondedPerBlock) k_bonded(Args a) {
 template <int IPL>
 struct IAtoms32 {
     float xh[IPL], yh[IPL], zh[IPL];
-    float c12[IPL], c6[IPL], q[IPL];
+    float a12[IPL], b6[IPL], q[IPL];     // 12 c12, 6 c6, q^
 };
 
 // A pair closer than sqrt(kCorrR2) by the high halves: redo the displacement
@@ -223,11 +231,11 @@ __device__ __forceinline__ void close_pair32(const IAtoms32<IPL>& I, int k, floa
         const double rinv = 1.0 / sqrt(rr);
         const double rinv2 = rinv * rinv;
         const double rinv6 = rinv2 * rinv2 * rinv2;
-        const double e12 = (double)I.c12[k] * (double)cj.x * rinv6 * rinv6;
-        const double e6 = (double)I.c6[k] * (double)cj.y * rinv6;
+        const double A = (double)I.a12[k] * (double)cj.x, B = (double)I.b6[k] * (double)cj.y;
+        const double u = A * rinv6 - B;
         const double ec = (double)I.q[k] * (double)pj.w * rinv;
-        e64 += (e12 - e6) + ec;
-        const double f = (12.0 * e12 - 6.0 * e6 + ec) * rinv2;
+        e64 += (u - B) * rinv6 * (1.0 / 12.0) + ec;
+        const double f = (u * rinv6 + ec) * rinv2;
         gx += f * ddx; gy += f * ddy; gz += f * ddz;
         fjx -= (float)(f * ddx); fjy -= (float)(f * ddy); fjz -= (float)(f * ddz);
         r2 = __builtin_inff();
@@ -245,7 +253,7 @@ __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const fl
                                        const IAtoms32<IPL>& I, float (&fx)[IPL], float (&fy)[IPL],
                                        float (&fz)[IPL], double (&gx)[IPL], double (&gy)[IPL],
                                        double (&gz)[IPL], float& fjx, float& fjy, float& fjz,
-                                       float& e32, double& e64) {
+                                       float& elj, float& ec32, double& e64) {
     uint64_t excl[IPL];
     if (MASKED) {
 #pragma unroll
@@ -277,12 +285,13 @@ __device__ __forceinline__ void tile32(const float4* __restrict__ s_xq, const fl
             const float rinv = __builtin_amdgcn_rsqf(r2);
             const float rinv2 = rinv * rinv;
             const float rinv6 = rinv2 * rinv2 * rinv2;
-            const float e6 = I.c6[k] * cj.y * rinv6;
-            const float e12 = I.c12[k] * cj.x * rinv6 * rinv6;
+            const float A = I.a12[k] * cj.x;
+            const float B = I.b6[k] * cj.y;
             const float ec = I.q[k] * pj.w * rinv;
-            const float lj = e12 - e6;
-            e32 += lj + ec;
-            const float f = __fmaf_rn(6.0f, lj + e12, ec) * rinv2;     // 12 e12 - 6 e6 + ec
+            const float u = __fmaf_rn(A, rinv6, -B);
+            const float f = __fmaf_rn(u, rinv6, ec) * rinv2;
+            elj = __fmaf_rn(u - B, rinv6, elj);
+            ec32 += ec;
             fx[k] = __fmaf_rn(f, dx, fx[k]);
             fy[k] = __fmaf_rn(f, dy, fy[k]);
             fz[k] = __fmaf_rn(f, dz, fz[k]);
@@ -327,8 +336,16 @@ __device__ __forceinline__ void block_energy_store(double e, double* out) {
 // HAS_FAR: the context has excluded pairs more than kExclWindow apart (the
 // kernel then checks every tile for a far-exclusion mask; the check costs a
 // few registers, so contexts without such pairs run the kernel without it).
+// Occupancy floor: with two atoms per lane the kernel fits 168 VGPRs, three
+// wavefronts per SIMD, but the compiler's own choice exceeds that by a few
+// registers and loses a wavefront.  (The far-exclusion variant would spill
+// at 168 and keeps the compiler's choice.)
+template <int IPL, bool HAS_FAR>
+constexpr int kPair32MinWaves = IPL == 2 && !HAS_FAR ? 3 : 1;
+
 template <int WAVES, int IPL, bool HAS_FAR>
-__global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(kPair32MinWaves<IPL, HAS_FAR>)))
+k_pair32(Args a) {
     const Layout& L = a.L;
     const int wg = blockIdx.x;
     const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
@@ -362,7 +379,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
         split(p[2], I.zh[k], lo.z);
         lo.w = 0.0f;
         s_ilo[il0 + k * 64] = lo;
-        I.c12[k] = C12[i]; I.c6[k] = C6[i]; I.q[k] = Q[i];
+        I.a12[k] = 12.0f * C12[i]; I.b6[k] = 6.0f * C6[i]; I.q[k] = Q[i];
         gx[k] = gy[k] = gz[k] = 0.0;
     }
     // bounding box of this wave's i-atoms: a j-tile whose box is farther than
@@ -415,7 +432,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
         float fx[IPL], fy[IPL], fz[IPL];
 #pragma unroll
         for (int k = 0; k < IPL; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
-        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, e32 = 0.0f;
+        float fjx = 0.0f, fjy = 0.0f, fjz = 0.0f, elj = 0.0f, ec32 = 0.0f;
         const float gxb = fmaxf(0.0f, fmaxf(s_jbox[0] - ib[3], ib[0] - s_jbox[3]));
         const float gyb = fmaxf(0.0f, fmaxf(s_jbox[1] - ib[4], ib[1] - s_jbox[4]));
         const float gzb = fmaxf(0.0f, fmaxf(s_jbox[2] - ib[5], ib[2] - s_jbox[5]));
@@ -427,19 +444,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair32(Args a) {
 #pragma unroll
             for (int k = 0; k < IPL; ++k) s_far[il0 + k * 64] = FM[(size_t)fu * B + il0 + k * 64];
             tile32<IPL, true, true, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx,
-                                          gy, gz, fjx, fjy, fjz, e32, e64);
+                                          gy, gz, fjx, fjy, fjz, elj, ec32, e64);
         } else if (t < t_masked_end)
             tile32<IPL, true, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx, gy, gz,
-                                    fjx, fjy, fjz, e32, e64);
+                                    fjx, fjy, fjz, elj, ec32, e64);
         else if (!far)
             tile32<IPL, false, true>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx, gy, gz,
-                                     fjx, fjy, fjz, e32, e64);
+                                     fjx, fjy, fjz, elj, ec32, e64);
         else
             tile32<IPL, false, false>(s_xq, s_c, s_lo, s_ilo, lane, il0, i0, J0, EX, s_far, I, fx, fy, fz, gx, gy, gz,
-                                      fjx, fjy, fjz, e32, e64);
+                                      fjx, fjy, fjz, elj, ec32, e64);
 #pragma unroll
         for (int k = 0; k < IPL; ++k) { gx[k] += fx[k]; gy[k] += fy[k]; gz[k] += fz[k]; }
-        e64 += e32;
+        e64 += (double)elj * (1.0 / 12.0) + (double)ec32;
         s_fj[wave][0][lane] = fjx;
         s_fj[wave][1][lane] = fjy;
         s_fj[wave][2][lane] = fjz;
@@ -481,11 +498,11 @@ __device__ __forceinline__ double rsqrt_finite(double x) {
 template <int IPL, bool MASKED, bool FAR = false>
 __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const double2* __restrict__ s_c,
                                        int lane, int J0, const double (&xi)[IPL], const double (&yi)[IPL],
-                                       const double (&zi)[IPL], const double (&c12i)[IPL],
-                                       const double (&c6i)[IPL], const double (&qi)[IPL],
+                                       const double (&zi)[IPL], const double (&a12i)[IPL],
+                                       const double (&b6i)[IPL], const double (&qi)[IPL],
                                        const uint64_t (&excl)[IPL], const uint64_t (&fmask)[IPL], const int (&idx)[IPL],
                                        double (&gx)[IPL], double (&gy)[IPL], double (&gz)[IPL],
-                                       double& fjx, double& fjy, double& fjz, double& e) {
+                                       double& fjx, double& fjy, double& fjz, double& elj, double& ecs) {
 #pragma unroll 2
     for (int s = 0; s < kTile; ++s) {
         const int js = lane + s;
@@ -509,12 +526,13 @@ __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const d
             const double rinv = MASKED ? rsqrt(r2) : rsqrt_finite(r2);
             const double rinv2 = rinv * rinv;
             const double rinv6 = rinv2 * rinv2 * rinv2;
-            const double e6 = c6i[k] * cj.y * rinv6;
-            const double e12 = c12i[k] * cj.x * rinv6 * rinv6;
+            const double A = a12i[k] * cj.x;
+            const double B = b6i[k] * cj.y;
             const double ec = qi[k] * pj.w * rinv;
-            const double lj = e12 - e6;
-            e += lj + ec;
-            const double f = (6.0 * (lj + e12) + ec) * rinv2;
+            const double u = fma(A, rinv6, -B);
+            const double f = fma(u, rinv6, ec) * rinv2;
+            elj = fma(u - B, rinv6, elj);
+            ecs += ec;
             gx[k] += f * dx; gy[k] += f * dy; gz[k] += f * dz;
             fjx -= f * dx; fjy -= f * dy; fjz -= f * dz;
         }
@@ -543,7 +561,7 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
     const uint64_t fnone[IPL] = {};
     const int I0 = ch.row * B;
 
-    double xi[IPL], yi[IPL], zi[IPL], c12i[IPL], c6i[IPL], qi[IPL], gx[IPL], gy[IPL], gz[IPL];
+    double xi[IPL], yi[IPL], zi[IPL], a12i[IPL], b6i[IPL], qi[IPL], gx[IPL], gy[IPL], gz[IPL];
     uint64_t excl[IPL];
     int idx[IPL];
 #pragma unroll
@@ -552,7 +570,7 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
         double p[3];
         load_pos(X, i - aoff, n, p);
         xi[k] = p[0]; yi[k] = p[1]; zi[k] = p[2];
-        c12i[k] = C12[i]; c6i[k] = C6[i]; qi[k] = Q[i];
+        a12i[k] = 12.0 * C12[i]; b6i[k] = 6.0 * C6[i]; qi[k] = Q[i];
         excl[k] = EX[i];
         idx[k] = i;
         gx[k] = gy[k] = gz[k] = 0.0;
@@ -560,7 +578,7 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
     __shared__ double4 s_xq[2 * kTile];
     __shared__ double2 s_c[2 * kTile];
     __shared__ double s_fj[WAVES][3][kTile];
-    double e = 0.0;
+    double elj = 0.0, ecs = 0.0;     // 12 x Lennard-Jones energy, Coulomb energy
     const int t_masked_end = (I0 + B) / kTile + 1;
     for (int t = ch.t_begin; t < ch.t_end; ++t) {
         const int J0 = t * kTile;
@@ -581,14 +599,14 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
             uint64_t fmask[IPL];
 #pragma unroll
             for (int k = 0; k < IPL; ++k) fmask[k] = FM[(size_t)fu * B + wave * 64 * IPL + k * 64 + lane];
-            tile64<IPL, true, true>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, fmask, idx, gx, gy, gz,
-                                    fjx, fjy, fjz, e);
+            tile64<IPL, true, true>(s_xq, s_c, lane, J0, xi, yi, zi, a12i, b6i, qi, excl, fmask, idx, gx, gy, gz,
+                                    fjx, fjy, fjz, elj, ecs);
         } else if (t < t_masked_end) {
-            tile64<IPL, true>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, fnone, idx, gx, gy, gz, fjx, fjy,
-                              fjz, e);
+            tile64<IPL, true>(s_xq, s_c, lane, J0, xi, yi, zi, a12i, b6i, qi, excl, fnone, idx, gx, gy, gz, fjx, fjy,
+                              fjz, elj, ecs);
         } else {
-            tile64<IPL, false>(s_xq, s_c, lane, J0, xi, yi, zi, c12i, c6i, qi, excl, fnone, idx, gx, gy, gz, fjx,
-                               fjy, fjz, e);
+            tile64<IPL, false>(s_xq, s_c, lane, J0, xi, yi, zi, a12i, b6i, qi, excl, fnone, idx, gx, gy, gz, fjx,
+                               fjy, fjz, elj, ecs);
         }
         s_fj[wave][0][lane] = fjx;
         s_fj[wave][1][lane] = fjy;
@@ -608,7 +626,7 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
         const int il = wave * 64 * IPL + k * 64 + lane;
         pi[3 * il] = gx[k]; pi[3 * il + 1] = gy[k]; pi[3 * il + 2] = gz[k];
     }
-    block_energy_store<WAVES>(e, at<double>(a.ws, L.off_ep) + wg);
+    block_energy_store<WAVES>(elj * (1.0 / 12.0) + ecs, at<double>(a.ws, L.off_ep) + wg);
 }
 
 // The FP64 kernel walks the chunks with a grid stride: in FP32 mode (and in
@@ -664,6 +682,7 @@ hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
         FF_PAIR_CASE(5)
         FF_PAIR_CASE(6)
         FF_PAIR_CASE(7)
+        FF_PAIR_CASE(8)
     default:
         return hipErrorInvalidValue;
     }

@@ -39,6 +39,9 @@ def _system(name):
         return s
     if name == "torsion300":
         return torsion_chain(300, 7)
+    if name == "crosslinked600":
+        from tests.systems import crosslinked_chain
+        return crosslinked_chain(600, 8)
     kind, seed = name.split("_")
     return chain_system(int(kind[5:]), int(seed))
 
@@ -70,6 +73,9 @@ CASES = {
     "chain300_23-cg-cd": ("chain300_23", "cg", {"cg_beta": "cd"}, 30, [(30, 1e-9)], None),
     "chain300_23-cg-ls": ("chain300_23", "cg", {"cg_beta": "ls"}, 30, [(30, 1e-9)], None),
     "chain300_23-cg-dy": ("chain300_23", "cg", {"cg_beta": "dy"}, 30, [(30, 1e-9)], None),
+    # exclusions more than 64 atoms apart (cross-links and the angles around them)
+    "crosslinked600-lbfgs": ("crosslinked600", "lbfgs", {}, 20, [(5, 1e-9), (12, 1e-8), (15, 1e-7), (20, 1e-5)],
+                             None),
 }
 
 

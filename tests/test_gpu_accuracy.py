@@ -6,7 +6,10 @@ modes are compared with the oracle's full evaluation: relative energy error,
 relative error of |grad E|_2 and of |grad E|_inf, and the largest component
 error relative to |grad E|_inf.  Gates: energy 1e-6 and gradient norms 1e-5
 relative in both modes (FP32 mode: where |grad E|_inf >= 1, as elsewhere);
-the printed table is the measured error (run with -s to see it).
+largest component error relative to |grad E|_inf: 1e-12 in FP64 mode and
+RC_FP32 in FP32 mode, a constant calibrated once on chain512 (start and
+relaxed point: at most 1.4e-6 measured) and frozen at about three times
+that.  The printed table is the measured error (run with -s to see it).
 """
 import numpy as np
 import pytest
@@ -19,6 +22,8 @@ from synth import config_system
 pytestmark = pytest.mark.gpu
 
 RELAX = {"chain512": 300, "chain10k": 200, "chain50k": 100}
+RC_FP64 = 1e-12
+RC_FP32 = 2.0 ** -18          # calibrated on chain512, then frozen
 
 
 @pytest.mark.parametrize("name", ["chain512", "chain10k", "chain50k"])
@@ -46,3 +51,4 @@ def test_error_against_the_oracle_per_workload(name):
             assert re <= 1e-6
             if prec == "fp64" or nir >= 1.0:
                 assert r2 <= 1e-5 and ri <= 1e-5
+            assert rc <= (RC_FP64 if prec == "fp64" else RC_FP32)

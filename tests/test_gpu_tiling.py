@@ -90,17 +90,3 @@ def test_far_exclusions_match_the_oracle_for_every_tiling(linked, cfg):
     assert abs(e32 - e_ref) <= 1e-6 * abs(e_ref)
     bound = 2.0 ** -16 * pair_force_sum[:, None] + 1e-9 * np.abs(g_ref).max()
     assert np.all(np.abs(g32 - g_ref) <= bound), np.abs(g32 - g_ref).max()
-
-
-def test_far_exclusions_minimization_follows_the_oracle():
-    s = crosslinked_chain(600, 8)
-    sysc = oracle.System(s)
-    ref = oracle.minimize(lambda v: oracle.energy_grad(sysc, v.reshape(-1, 3)), s["x"].ravel(),
-                          oracle.MinParams(method=oracle.LBFGS, max_iter=20))
-    ctx = ff.Context(s, m_max=10)
-    x = torch.tensor(s["x"], dtype=torch.float64, device="cuda")
-    print("far exclusions minimize", flush=True)
-    r = ctx.minimize(x, "lbfgs", max_iter=20)
-    tr = ctx.trace()
-    assert r["iters"] == ref.iters == 20 and r["evals"] == ref.evals
-    np.testing.assert_allclose(tr[:20, 0], [t[0] for t in ref.trace], rtol=1e-9)
