@@ -23,11 +23,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 38            # algorithmic flops of one pair (energy + gradient)
-# Non-packed FP32 vector peak of MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop
-# (FMA) x 2.4 GHz.  Packed FP32 (which doubles it to 157.3 TFLOP/s) is
-# switched off in this build.
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-PEAK_FP32_PACKED_TFLOPS = 157.3
+# Published MI355X vector peaks (TFLOP/s): FP32 157.3 (two FP32 operations per
+# lane and cycle, i.e. packed FP32) and FP64 78.6.  This build issues no packed
+# FP32, so its FP32 ceiling is the scalar issue rate, 256 CU x 4 SIMD x 16
+# lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s, reported beside the peak.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+SCALAR_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 PAIR_SOURCES = ["paper_1810_03358_amd/csrc/ff_pair.hip", "paper_1810_03358_amd/csrc/ff_internal.h"]
@@ -62,10 +64,23 @@ def non_excluded_pairs(n: int) -> int:
     return n * (n - 1) // 2 - max(0, n - 1) - max(0, n - 2)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(system, x0, seconds: float = 15.0):
     """The FP64 CPU oracle, timed on a bounded sample of the same workload:
-    full energy+gradient evaluations at the start point, repeated until about
-    `seconds` of CPU time (at least one)."""
+    full energy+gradient evaluations at the start point on all the oracle's
+    threads, repeated until about `seconds` of CPU time (at least one); then
+    one thread on a sample of gradient rows (each row is the same O(N) loop a
+    full evaluation runs N times), scaled to a full evaluation."""
+    import numpy as np
     import oracle
     sysc = oracle.System(system)
     n = 0
@@ -76,9 +91,29 @@ def cpu_baseline(system, x0, seconds: float = 15.0):
         dt = time.perf_counter() - t0
         if dt >= seconds or n >= 50:
             break
-    return {"value": n / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} full FP64 energy+gradient evaluation(s) of the {system['n_atoms']}-atom start point "
-                      f"({dt:.1f} s)"}
+    threads = oracle.num_threads()
+    natoms = system["n_atoms"]
+    oracle.set_num_threads(1)
+    rows, dt1 = 64, 0.0
+    try:
+        while True:
+            atoms = np.linspace(0, natoms - 1, min(rows, natoms)).astype(np.int32)
+            t1 = time.perf_counter()
+            oracle.atom_gradients(sysc, x0, atoms)
+            dt1 = time.perf_counter() - t1
+            if dt1 >= seconds / 5 or len(atoms) == natoms:
+                break
+            rows *= 4
+    finally:
+        oracle.set_num_threads(threads)
+    one_core = len(atoms) / (dt1 * natoms)
+    return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} full FP64 energy+gradient evaluation(s) of the {natoms}-atom start point "
+                      f"({dt:.1f} s)",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core": {"value": one_core, "unit": "evals/s", "cores": 1,
+                         "sample": f"{len(atoms)} of {natoms} gradient rows on one thread ({dt1:.1f} s), "
+                                   f"scaled to a full evaluation"}}
 
 
 def batch_bench(args):
@@ -134,11 +169,38 @@ def batch_bench(args):
     ctx.close()
 
 
+def oracle_solve(system, method: str, max_iter: int, threads: int | None = None):
+    """The FP64 oracle minimizing the same system with the same method and
+    stopping rule, timed on the host (all the oracle's threads, or `threads`)."""
+    import oracle
+    sysc = oracle.System(system)
+    code = {"gd": oracle.GD, "fgm": oracle.FGM, "cg": oracle.CG, "lbfgs": oracle.LBFGS}[method]
+    p = oracle.MinParams(method=code, m=10, tol=1e-3, max_iter=max_iter)
+    keep = oracle.num_threads()
+    if threads:
+        oracle.set_num_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        r = oracle.minimize(lambda v: oracle.energy_grad(sysc, v.reshape(-1, 3)), system["x"].ravel(), p)
+        wall = time.perf_counter() - t0
+        used = oracle.num_threads()
+    finally:
+        oracle.set_num_threads(keep)
+    term = {oracle.CONVERGED: "converged", oracle.MAX_ITER: "max_iter", oracle.LS_FAILED: "ls_failed",
+            oracle.NONFINITE_START: "nonfinite_start"}.get(r.term, str(r.term))
+    return {"time_s": wall, "cores": used, "term": term, "iters": r.iters, "evals": r.evals, "energy": r.f,
+            "grad_inf": float(abs(r.g).max()), "x": r.x}
+
+
 def solve_bench(args):
-    """One named chain minimized by L-BFGS (m = 10, LS_PAR) from its start to
-    |grad E|_inf < 1e-3 (or --solve-iters iterations) in one ff_minimize
-    call, start point resident in HBM; reports the wall time and the
-    certified end point."""
+    """One named chain minimized from its start to |grad E|_inf < 1e-3 (or
+    --solve-iters iterations) in one ff_minimize call by --method (m = 10;
+    LS_PAR, FGM: LS_H), start point resident in HBM; reports the wall time and
+    the end point, certified by an FP64 evaluation after the timed region.
+    --oracle also runs the FP64 oracle on the host with the same method and
+    stopping rule (all threads, and one thread with --oracle-one-core) and
+    compares the two end points."""
+    import numpy as np
     import torch
     import paper_1810_03358_amd as ff
     from synth import config_system
@@ -156,11 +218,12 @@ def solve_bench(args):
         t0 = time.perf_counter()
         iters = evals = evals64 = 0
         while True:
-            r = ctx.minimize(x, "lbfgs", m=10, tol=1e-3, max_iter=min(5000, args.solve_iters - iters),
+            r = ctx.minimize(x, args.method, m=10, tol=1e-3, max_iter=min(5000, args.solve_iters - iters),
                              precision=args.precision, resume=iters > 0, certify=False, stream=stream)
             iters += r["iters"]
             evals, evals64 = r["evals"], r["evals_fp64"]
-            print(f"solve: {iters} iterations, {r['term_name']}, |g|_inf {r['grad_inf']:.3e}", file=sys.stderr,
+            print(f"solve: {iters} iterations, {r['term_name']}, E {r['energy']:.9e}, |g|_inf {r['grad_inf']:.3e}, "
+                  f"{evals} evaluations ({evals64} FP64), {time.perf_counter() - t0:.1f} s", file=sys.stderr,
                   flush=True)
             if r["term"] != ff.FF_MAX_ITER or iters >= args.solve_iters:
                 break
@@ -170,15 +233,32 @@ def solve_bench(args):
         torch.cuda.synchronize()
         r = dict(r, iters=iters, evals=evals, evals_fp64=evals64, energy=float(e.cpu()[0]),
                  grad_inf=float(g.abs().max().cpu()))
+        x_gpu = x.cpu().numpy()
+    ls = "LS_H" if args.method == "fgm" else "LS_PAR"
     out = {
         "metric": "time to |grad E|_inf<1e-3 (one system)", "value": wall, "unit": "s", "n_gpus": 1,
         "higher_is_better": False, "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "atoms": s["n_atoms"], "seed": s["seed"],
-                   "method": f"L-BFGS m=10, LS_PAR, tol 1e-3, max_iter {args.solve_iters}"},
+                   "method": f"{args.method} m=10, {ls}, tol 1e-3, max_iter {args.solve_iters}"},
         "term": r["term_name"], "iters": r["iters"], "evals": r["evals"], "evals_fp64": r["evals_fp64"],
         "energy": r["energy"], "grad_inf": r["grad_inf"], "evals_per_s": r["evals"] / wall,
     }
+    if args.oracle:
+        runs = [oracle_solve(s, args.method, args.solve_iters)]
+        if args.oracle_one_core:
+            runs.append(oracle_solve(s, args.method, args.solve_iters, threads=1))
+        o = runs[0]
+        rmsd = float(np.sqrt(((x_gpu - o["x"].reshape(-1, 3)) ** 2).sum(1).mean()))
+        out["cpu_baseline"] = {"value": o["time_s"], "unit": "s", "cores": o["cores"], "kind": "oracle",
+                               "sample": "the whole solve: same system, method and stopping rule, FP64",
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        if len(runs) > 1:
+            out["cpu_baseline"]["one_core"] = {"value": runs[1]["time_s"], "unit": "s", "cores": 1}
+        out["oracle"] = {k: v for k, v in o.items() if k != "x"}
+        out["vs_oracle"] = {"energy_rel_diff": abs(r["energy"] - o["energy"]) / abs(o["energy"]),
+                            "rmsd_per_atom_A": rmsd, "same_term": r["term_name"] == o["term"],
+                            "time_ratio_oracle_over_gpu": o["time_s"] / wall}
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -269,6 +349,9 @@ def main():
     ap.add_argument("--solve", action="store_true",
                     help="chain512/10k/50k: minimize to |grad E|_inf < 1e-3 and report the time instead")
     ap.add_argument("--solve-iters", type=int, default=100_000, help="--solve: iteration limit")
+    ap.add_argument("--method", default="lbfgs", choices=["lbfgs", "gd", "fgm", "cg"], help="--solve: method")
+    ap.add_argument("--oracle", action="store_true", help="--solve: also run the FP64 oracle on the host")
+    ap.add_argument("--oracle-one-core", action="store_true", help="--solve --oracle: and on one thread")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--test-chains", type=int, default=8, help="learned: held-out chains")
     ap.add_argument("--test-offset", type=int, default=0, help="learned: index of the first held-out chain")
@@ -377,9 +460,9 @@ def main():
             "kernel": "k_pair32" if args.precision == "fp32" else "k_pair64",
             "bound": "alu",
             "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS if args.precision == "fp32" else 78.6,
+            "peak": PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / (PEAK_FP32_TFLOPS if args.precision == "fp32" else 78.6),
+            "frac": achieved / (PEAK_FP32_TFLOPS if args.precision == "fp32" else PEAK_FP64_TFLOPS),
             "traffic": measured_traffic(args.workload, args.precision),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel_ms": ms_pair,
@@ -387,7 +470,8 @@ def main():
         },
     }
     if args.precision == "fp32":
-        out["roofline"]["frac_of_packed_fp32_peak"] = achieved / PEAK_FP32_PACKED_TFLOPS
+        out["roofline"]["scalar_issue_peak"] = SCALAR_ISSUE_TFLOPS
+        out["roofline"]["frac_of_scalar_issue_peak"] = achieved / SCALAR_ISSUE_TFLOPS
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, s["x"], args.cpu_seconds)
     print(json.dumps(out), flush=True)

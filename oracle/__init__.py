@@ -18,7 +18,7 @@ shares no code with the HIP path.
 """
 from . import learn  # noqa: F401
 from .energy import (System, energy_grad, energy_terms, atom_gradients, num_threads, build,  # noqa: F401
-                     energy_profile, abs_pair_force)
+                     energy_profile, abs_pair_force, set_num_threads)
 from .minimize import (  # noqa: F401
     MinParams, MinResult, minimize, ls_par, ls_h, lbfgs_direction, fgm_coefficients, ogm_t_next,
     GD, FGM, CG, LBFGS, HB, OGM, LS_PAR, LS_H, cg_beta,

@@ -54,6 +54,8 @@ def _load():
                                               C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double)]
         lib.oracle_atom_gradients.restype = C.c_int
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_set_num_threads.argtypes = [C.c_int]
+        lib.oracle_set_num_threads.restype = None
         lib.oracle_abs_pair_force.argtypes = [C.POINTER(_CSystem), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.oracle_abs_pair_force.restype = C.c_int
         _lib = lib
@@ -140,6 +142,11 @@ def abs_pair_force(sys, x):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads used by later oracle calls from this thread."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def energy_profile(system, x, t):

@@ -278,6 +278,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the following calls from this thread (timing on fewer cores). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Energy terms [stretch, bend, torsion, coulomb, vdw] at x ([N][3]), and the
  * gradient ([N][3]) if grad != NULL.  Returns 0, -1 on a bad index or size,
  * -2 on allocation failure. */
