@@ -141,13 +141,17 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     if (n_tot > (1 << 28)) return false;
     if (ft.cap < far_capacity(s, n_sys)) return false;
     L.n_sys = n_sys;
-    // defaults from sweeps on MI355X: small systems and batches use 64-atom
-    // blocks; large systems 256-atom blocks with two atoms per lane, and from
-    // 32768 atoms on four per lane in the FP64 kernel (6 % faster than one
-    // at 50k atoms, 7 % slower at 10k)
+    // defaults from sweeps of whole FP32 and FP64 evaluations on MI355X
+    // (2,500 to 50,000 atoms, every configuration x chunks of 1, 2, 4):
+    // batches and small systems use 64-atom blocks; up to 12,288 atoms
+    // 256-atom blocks with one atom per lane and one j-tile per workgroup
+    // (enough workgroups to fill the chip: 0.085 instead of 0.105 ms per FP32
+    // evaluation at 10k atoms); above, two atoms per lane in FP32 and four in
+    // FP64, with chunks of two j-tiles from 32,768 atoms on
     if (n_sys > 1) { L.cfg = 0; L.chunk = 4; }
     else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
-    else if (n_max < 32768) { L.cfg = 4; L.chunk = 2; }
+    else if (n_max < 12288) { L.cfg = 1; L.chunk = 1; }
+    else if (n_max < 32768) { L.cfg = 8; L.chunk = 1; }
     else { L.cfg = 8; L.chunk = 2; }
     if (cfg_req >= 0) {
         if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk) return false;
