@@ -179,9 +179,19 @@ def oracle_solve(system, method: str, max_iter: int, threads: int | None = None)
     keep = oracle.num_threads()
     if threads:
         oracle.set_num_threads(threads)
+    state = {"evals": 0, "last": time.perf_counter()}
+
+    def fg(v):
+        state["evals"] += 1
+        now = time.perf_counter()
+        if now - state["last"] >= 10.0:
+            state["last"] = now
+            print(f"oracle {method}: {state['evals']} evaluations, {now - t0:.0f} s", file=sys.stderr, flush=True)
+        return oracle.energy_grad(sysc, v.reshape(-1, 3))
+
     try:
         t0 = time.perf_counter()
-        r = oracle.minimize(lambda v: oracle.energy_grad(sysc, v.reshape(-1, 3)), system["x"].ravel(), p)
+        r = oracle.minimize(fg, system["x"].ravel(), p)
         wall = time.perf_counter() - t0
         used = oracle.num_threads()
     finally:

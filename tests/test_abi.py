@@ -250,3 +250,26 @@ def test_noalloc_scratch_limit_matches_the_header():
     text = open(os.path.join(INCLUDE, "ff.h")).read()
     m = re.search(r"#define FF_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == N.FF_NOALLOC_SCRATCH_BYTES
+
+
+def test_bench_cpu_baseline_legs_on_a_small_chain():
+    """The benchmark's oracle legs (no GPU): the all-threads rate, the
+    one-thread row sample with the CPU model, and the timed oracle solve
+    that --solve --oracle reports beside the GPU's."""
+    import sys
+    root = os.path.dirname(INCLUDE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import bench
+    import oracle
+    s = chain_system(120, 3)
+    cb = bench.cpu_baseline(s, s["x"], seconds=0.2)
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] == oracle.num_threads()
+    assert cb["one_core"]["cores"] == 1 and cb["one_core"]["value"] > 0 and cb["cpu_model"]
+    threads = oracle.num_threads()
+    o = bench.oracle_solve(s, "lbfgs", 50, threads=1)
+    assert oracle.num_threads() == threads          # restored
+    assert o["cores"] == 1 and o["iters"] == 50 and o["term"] == "max_iter" and o["x"].shape == (360,)
+    ref = oracle.minimize(lambda v: oracle.energy_grad(oracle.System(s), v.reshape(-1, 3)), s["x"].ravel(),
+                          oracle.MinParams(method=oracle.LBFGS, m=10, tol=1e-3, max_iter=50))
+    assert o["energy"] == ref.f and o["evals"] == ref.evals
