@@ -44,7 +44,8 @@ struct ff_ctx {
     std::vector<SysInfo> sys;    // host copy of the per-system info
     int32_t* host_flag;          // pinned: polled batch counters
     Ctl* host_ctl;               // pinned copy of one control block
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;     // cycles with both pair kernels (FP32 mode)
+    hipGraphExec_t graph64 = nullptr;   // cycles with the FP64 pair kernel only
     hipStream_t own = nullptr;   // private stream: graph capture, and calls made on the NULL stream
     int last_method = -1, last_m = -1, last_prec = -1;
 };
@@ -721,6 +722,7 @@ ff_status ff_create(const ff_system* s, void* workspace, size_t ws_bytes, int32_
 ff_status ff_destroy(ff_ctx* c) {
     if (!c) return FF_OK;
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph64) (void)hipGraphExecDestroy(c->graph64);
     if (c->own) (void)hipStreamDestroy(c->own);
     (void)hipHostFree(c->host_flag);
     (void)hipHostFree(c->host_ctl);
@@ -785,7 +787,9 @@ ff_status ff_energy_grad_noalloc(const ff_system* sys, const double* xyz, double
 
 static constexpr int kCyclesPerGraph = 4;
 
-static ff_status build_graph(ff_ctx* c) {
+// with32 = false leaves the FP32 pair kernel out: FP64 runs, and FP32-mode
+// runs once every system has switched to FP64 (the switch is final).
+static ff_status build_graph(ff_ctx* c, bool with32, hipGraphExec_t* out) {
     hipStream_t st = c->own;
     Args a{};
     a.L = c->L;
@@ -797,7 +801,7 @@ static ff_status build_graph(ff_ctx* c) {
     for (int k = 0; k < kCyclesPerGraph && e == hipSuccess; ++k) {
         e = launch_cycle_vec(a, 0, st);
         if (e == hipSuccess) e = launch_bonded(a, st);
-        if (e == hipSuccess) e = launch_pair(a, 1, st);
+        if (e == hipSuccess && with32) e = launch_pair(a, 1, st);
         if (e == hipSuccess) e = launch_pair(a, 0, st);
         if (e == hipSuccess) e = launch_finalize(a, st);
         if (e == hipSuccess) e = launch_cycle_vec(a, 1, st);
@@ -805,9 +809,9 @@ static ff_status build_graph(ff_ctx* c) {
     hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return fail(FF_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(FF_ERR_HIP, "graph capture end: %s", hipGetErrorString(e2));
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) { c->graph = nullptr; return fail(FF_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
+    if (e != hipSuccess) { *out = nullptr; return fail(FF_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e)); }
     return FF_OK;
 }
 
@@ -866,10 +870,18 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
             HIP_TRY(hipMemcpyAsync(x0 + 3 * (size_t)c->sys[k].aoff, xyz + 3 * (size_t)c->sys[k].uoff,
                                    3 * (size_t)c->sys[k].n * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(launch_kick(a, d, resume ? 1 : 0, trace_buffer(c), kTraceCap, st));
-    if (!c->graph) {
-        ff_status gs = build_graph(c);
+    if (!c->graph64) {
+        ff_status gs = build_graph(c, false, &c->graph64);
         if (gs) return gs;
     }
+    if (p->precision == FF_FP32_ACC64 && !c->graph) {
+        ff_status gs = build_graph(c, true, &c->graph);
+        if (gs) return gs;
+    }
+    // FP32 mode runs the graph with both pair kernels until every unfinished
+    // system has switched to FP64 evaluations (the poll reports it); a
+    // resumed run may already be there
+    hipGraphExec_t graph = p->precision == FF_FP32_ACC64 ? c->graph : c->graph64;
     c->last_method = p->method;
     c->last_m = p->m;
     c->last_prec = p->precision;
@@ -879,10 +891,11 @@ ff_status ff_minimize(ff_ctx* c, double* xyz, const ff_min_params* p, ff_min_res
     int batch = 1;              // graph launches (kCyclesPerGraph cycles each) between polls
     uint32_t last_evals = 0xffffffffu;
     for (;;) {
-        for (int k = 0; k < batch; ++k) HIP_TRY(hipGraphLaunch(c->graph, st));
+        for (int k = 0; k < batch; ++k) HIP_TRY(hipGraphLaunch(graph, st));
         HIP_TRY(hipMemcpyAsync(hs, dev_state, sizeof(BatchState), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if ((int)hs[0] >= L.n_sys) break;
+        if (hs[2] >= (uint32_t)L.n_sys) graph = c->graph64;
         // every cycle that is not only an accept pass evaluates; a batch of
         // cycles without a new evaluation means the decision logic stopped
         if (hs[1] == last_evals) return fail(FF_ERR_HIP, "minimizer stalled (%u of %d systems done)", hs[0], L.n_sys);

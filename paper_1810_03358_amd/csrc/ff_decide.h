@@ -78,7 +78,17 @@ __device__ inline void request_eval(Ctl* c, int mode, int target, int want_slope
     c->accept = 0;
 }
 
+// The system needs no FP32 evaluation any more (it switched to FP64 or it
+// stops): counted once per ff_minimize call, so that the host can leave the
+// FP32 pair kernel out of the iteration graph once every system is there.
+__device__ inline void release_fp32(Ctl* c) {
+    if (c->fp32_released) return;
+    c->fp32_released = 1;
+    if (c->batch) atomicAdd(&c->batch->n_fp64, 1u);
+}
+
 __device__ inline void finish_done(Ctl* c, int slot) {
+    release_fp32(c);
     c->result_slot = slot;
     c->phase = PH_DONE;
     c->done = 1;
@@ -88,6 +98,7 @@ __device__ inline void finish_done(Ctl* c, int slot) {
 }
 
 __device__ inline void finish(Ctl* c, int term) {
+    release_fp32(c);
     c->term = term;
     const int slot = (c->p.method == M_FGM && c->best >= 0) ? c->best : c->cur;
     if (c->p.precision == P_FP32 && c->p.certify && term != T_NONFINITE && c->slot_prec[slot] != P_FP64) {
@@ -116,6 +127,7 @@ __device__ inline void ogm_restart(Ctl* c) {
 // and their products with g would no longer match the FP64 gradient, so the
 // next direction starts again from -g.
 __device__ inline void escalate(Ctl* c, int slot) {
+    release_fp32(c);
     c->escalated = 1;
     c->prec_now = P_FP64;
     c->phase = PH_REEVAL64;

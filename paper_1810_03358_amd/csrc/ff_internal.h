@@ -72,6 +72,8 @@ enum LsHStage : int32_t { LSH_F0 = 0, LSH_F1 = 1, LSH_SHRINK = 2 };
 struct BatchState {
     uint32_t n_done;      // systems finished in the current ff_minimize
     uint32_t evals;       // evaluations of all systems (progress watchdog)
+    uint32_t n_fp64;      // systems whose mixed-precision run has switched to FP64
+    uint32_t pad_;
 };
 
 struct MinParamsDev {
@@ -114,6 +116,7 @@ struct Ctl {
     int32_t prec_now;                      // precision of the running phase
     int32_t escalated;
     int32_t stall32;                       // an FP32 step gained less than FP32 can resolve
+    int32_t fp32_released;                 // counted in BatchState::n_fp64 (needs no FP32 evaluation any more)
     double h_prev;
     // line search
     int32_t ls_kind, ls_hstage, ls_base, ls_best, ls_ntrials, ls_primary, ls_fallback_done;

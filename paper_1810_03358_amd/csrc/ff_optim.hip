@@ -525,6 +525,8 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
             c->trace_cap = trace_cap;
             c->n_trace = 0;
             c->iters_base = c->iters;
+            c->fp32_released = 0;
+            if (c->escalated) release_fp32(c);
             need_dir = p.method == M_LBFGS && c->hist_n > 0;
         }
         __syncthreads();
@@ -557,6 +559,7 @@ __global__ void k_kick(Args a, MinParamsDev p, int resume, double* trace, int tr
     c->prec_now = p.precision;
     c->escalated = 0;
     c->stall32 = 0;
+    c->fp32_released = 0;
     c->h_prev = p.h_init;
     c->steepest = 1;
     c->theta_prev = 1.0;
@@ -578,6 +581,7 @@ __global__ void k_reset_batch(Args a) {
     BatchState* b = at<BatchState>(a.ws, a.L.off_batch);
     b->n_done = 0u;
     b->evals = 0u;
+    b->n_fp64 = 0u;
 }
 
 // Marks every system idle (after ff_create).
