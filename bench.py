@@ -351,13 +351,73 @@ def learned_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def spread_bench(args):
+    """How far apart correct runs end: 32 chains of 2,000 atoms (the learned
+    test recipe: seed 300000 + k, compacted start for even k, extended for
+    odd k), minimized together by L-BFGS (m = 10) to |grad E|_inf < 1e-3 in
+    FP64 and in FP32 mode, five times each: under four tilings (four
+    summation orders of the same sums) and from the start moved by 1e-12 A
+    (seeded normal).  Reports, per pair of runs, the relative difference of
+    the final energies and the ratio of the iteration counts: the scale of a
+    rounding-level change of the path, against which a criterion such as
+    "equal final energy within 1e-4" can be judged."""
+    import numpy as np
+    import torch
+    import paper_1810_03358_amd as ff
+    from synth import chain_system
+
+    k_sys = 32
+    systems = [chain_system(2000, 300_000 + k, compact=k % 2 == 0) for k in range(k_sys)]
+    x0 = np.concatenate([s["x"] for s in systems])
+    moved = x0 + 1e-12 * np.random.default_rng(5).standard_normal(x0.shape)
+    variants = [((0, 4), x0, "tiling (0, 4)"), ((0, 1), x0, "tiling (0, 1)"), ((1, 1), x0, "tiling (1, 1)"),
+                ((5, 1), x0, "tiling (5, 1)"), ((0, 4), moved, "tiling (0, 4), start moved 1e-12 A")]
+    out = {"metric": "spread of final energies under rounding-level path changes", "unit": "relative",
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "spread32x2000", "systems": k_sys, "atoms": 2000,
+                      "starts": "even k compacted, odd k extended, seeds 300000+k",
+                      "method": f"L-BFGS m=10, LS_PAR, tol 1e-3, max_iter {args.learned_iters}"},
+           "modes": {}}
+    for mode in ("fp64", "fp32"):
+        E, iters, conv = [], [], []
+        for tiling, start, label in variants:
+            ctx = ff.Context(systems, m_max=10, device=torch.device("cuda:0"), tiling=tiling)
+            x = torch.tensor(start, dtype=torch.float64, device="cuda:0").contiguous()
+            res = ctx.minimize(x, "lbfgs", m=10, tol=1e-3, max_iter=args.learned_iters, precision=mode)
+            ctx.close()
+            E.append([r["energy"] for r in res])
+            iters.append([r["iters"] for r in res])
+            conv.append(sum(r["term"] == ff.FF_CONVERGED for r in res))
+            print(f"{mode} {label}: {conv[-1]} of {k_sys} converged, median {np.median(iters[-1]):.0f} iterations",
+                  file=sys.stderr, flush=True)
+        E, iters = np.array(E), np.array(iters, dtype=float)
+        pairs = []
+        for a in range(len(variants)):
+            for b in range(a + 1, len(variants)):
+                d = np.abs(E[b] - E[a]) / np.abs(E[a])
+                pairs.extend(d.tolist())
+        pairs = np.array(pairs)
+        spread = (E.max(0) - E.min(0)) / np.abs(np.median(E, 0))
+        ratio = iters.max(0) / iters.min(0)
+        out["modes"][mode] = {
+            "runs": [v[2] for v in variants], "converged_per_run": conv,
+            "median_iters_per_run": np.median(iters, 1).tolist(),
+            "pairwise_rel_energy_difference_median": float(np.median(pairs)),
+            "pairwise_within_1e-4": f"{int((pairs < 1e-4).sum())} of {len(pairs)}",
+            "per_system_rel_spread_median": float(np.median(spread)),
+            "per_system_rel_spread_min": float(spread.min()),
+            "per_system_max_over_min_iterations_median": float(np.median(ratio)),
+            "per_system_max_over_min_iterations_max": float(ratio.max())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="chain50k",
-                    choices=["chain512", "chain10k", "chain50k", "batch256", "learned"])
+                    choices=["chain512", "chain10k", "chain50k", "batch256", "learned", "spread"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=60_000, help="batch256: iteration limit per system")
@@ -371,7 +431,7 @@ def main():
     ap.add_argument("--test-chains", type=int, default=8, help="learned: held-out chains")
     ap.add_argument("--test-offset", type=int, default=0, help="learned: index of the first held-out chain")
     ap.add_argument("--test-atoms", type=int, default=10_000, help="learned: atoms per held-out chain")
-    ap.add_argument("--learned-iters", type=int, default=60_000, help="learned: iteration limit per run")
+    ap.add_argument("--learned-iters", type=int, default=60_000, help="learned, spread: iteration limit per run")
     ap.add_argument("--weights", default=None, help="learned: network file (default: the shipped one)")
     ap.add_argument("--no-control", action="store_true", help="learned: skip the restart-only control")
     ap.add_argument("--probe-iters", type=int, default=None,
@@ -391,6 +451,9 @@ def main():
         return
     if args.workload == "learned":
         learned_bench(args)
+        return
+    if args.workload == "spread":
+        spread_bench(args)
         return
     if args.solve:
         solve_bench(args)

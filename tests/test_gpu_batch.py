@@ -117,3 +117,26 @@ def test_batch_mixed_precision_cycles():
     e_ref, g_ref = oracle.energy_grad(chain, xs[:400])
     assert res[0]["energy"] == pytest.approx(e_ref, rel=1e-9)
     assert res[0]["grad_inf"] == pytest.approx(np.abs(g_ref).max(), rel=1e-6)
+
+
+def test_batch_fp32_resume_across_the_fp64_switch():
+    """FP32 mode on two chains that both switch to FP64 evaluations before
+    they converge: one call, and the same run cut short after both have
+    switched and then resumed, end bit-identical.  Once every system of a
+    batch has switched (or stopped), cycles run without the FP32 pair
+    kernel; on resume that state is rebuilt from the stored control blocks."""
+    systems = [chain_system(120, 31), chain_system(150, 32)]
+    ctx = ff.Context(systems, m_max=10)
+    xa = concat(systems)
+    ra = ctx.minimize(xa, "lbfgs", max_iter=5000, precision="fp32")
+    assert all(r["term"] == ff.FF_CONVERGED and r["evals_fp64"] >= 1 for r in ra)
+    cut = min(r["iters"] for r in ra) - 3
+    ctxb = ff.Context(systems, m_max=10)
+    xb = concat(systems)
+    rb1 = ctxb.minimize(xb, "lbfgs", max_iter=cut, precision="fp32")
+    assert all(r["evals_fp64"] >= 1 for r in rb1), [r["evals_fp64"] for r in rb1]
+    rb2 = ctxb.minimize(xb, "lbfgs", max_iter=5000, precision="fp32", resume=True)
+    np.testing.assert_array_equal(xb.cpu().numpy(), xa.cpu().numpy())
+    for a, b1, b2 in zip(ra, rb1, rb2):
+        assert b2["term"] == a["term"] and b1["iters"] + b2["iters"] == a["iters"]
+        assert b2["energy"] == a["energy"]
