@@ -175,9 +175,11 @@ int32_t ff_batch_size(const ff_ctx *ctx);
 
 /* Tiling of the pair kernel.  The pair matrix of each system is cut into
  * I-blocks of `block` atoms against j-tiles of 64 atoms, and one workgroup
- * walks `chunk` consecutive j-tiles of one I-block; a tile configuration fixes
- * the block size and the wavefronts and i-atoms per lane of the FP32 and FP64
- * kernels.  ff_create / ff_create_batch choose one from the system sizes; the
+ * walks `chunk` consecutive j-tiles of one I-block; with chunk > 1 the last
+ * sixteenth of each I-block's j-tiles (at least one) goes to one-tile chunks
+ * that end the launch, so that it drains on short workgroups.  A tile
+ * configuration fixes the block size and the wavefronts and i-atoms per lane
+ * of the FP32 and FP64 kernels.  ff_create / ff_create_batch choose one from the system sizes; the
  * functions below name one explicitly.  The tiling changes only speed and the
  * summation order of the pair partials (results agree to rounding). */
 int32_t ff_num_tile_configs(void);

@@ -127,6 +127,20 @@ static void far_exclusions(const ff_system& s, int aoff, FarTmp& ft) {
 // I-blocks so that small systems are padded to a multiple of 64 only.
 // `sys` receives n_sys entries; `ft` the far pairs and their units.
 // energy_only: no optimizer vectors (the layout serves ff_energy_grad only).
+// The chunks of one I-block with T j-tiles: `full` chunks of c tiles, one of
+// `rem` (< c) tiles if rem > 0, then `tail` one-tile chunks (c > 1 only).
+struct RowSplit {
+    int full, rem, tail;
+    int count() const { return full + (rem > 0 ? 1 : 0) + tail; }
+};
+static RowSplit row_split(int T, int c) {
+    RowSplit r{0, 0, 0};
+    r.tail = c > 1 ? std::min(T, (T + kTailDiv - 1) / kTailDiv) : 0;
+    r.full = (T - r.tail) / c;
+    r.rem = (T - r.tail) % c;
+    return r;
+}
+
 static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, SysInfo* sys, FarTmp& ft,
                         int32_t cfg_req = -1, int32_t chunk_req = 0, bool energy_only = false) {
     std::memset(&L, 0, sizeof L);
@@ -177,7 +191,7 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
         for (int b = 0; b < si.nb; ++b) {
             const int t0 = b * L.block / kTile;
             units += nt - t0;
-            chunks += (nt - t0 + L.chunk - 1) / L.chunk;
+            chunks += row_split(nt - t0, L.chunk).count();
         }
         si.n_chunks = chunks - si.chunk0;
         si.n_bonds = s[k].n_bonds;
@@ -373,10 +387,12 @@ static ff_status pack_static(const ff_system* systems, int32_t n_sys, const Layo
             qf[g] = (float)qd[g];
         }
     }
-    // tile tables (global I-block and j-tile indices)
+    // tile tables (global I-block and j-tile indices): rows, then the chunks
+    // in launch order (three passes: full-length chunks, shorter remainders,
+    // one-tile chunks; each pass row by row)
     ChunkInfo* chunks = at<ChunkInfo>(img, L.off_chunks);
     RowInfo* rows = at<RowInfo>(img, L.off_rows);
-    int unit = 0, nch = 0;
+    int unit = 0, slot = 0, nch = 0;
     for (int k = 0; k < n_sys; ++k) {
         const SysInfo& si = sys[k];
         const int tile0 = si.aoff / kTile, nt = si.np / kTile;
@@ -385,20 +401,43 @@ static ff_status pack_static(const ff_system* systems, int32_t n_sys, const Layo
             const int t0 = tile0 + b * L.block / kTile, t_end = tile0 + nt;
             rows[row].unit_start = unit;
             rows[row].t0 = t0;
-            rows[row].chunk_start = nch;
-            for (int t = t0; t < t_end; t += L.chunk) {
-                ChunkInfo& c = chunks[nch++];
-                c.row = row;
-                c.t_begin = t;
-                c.t_end = std::min(t + L.chunk, t_end);
-                c.unit_base = unit + (t - t0);
-                c.sys = k;
-            }
-            rows[row].n_chunks = nch - rows[row].chunk_start;
+            rows[row].chunk_start = slot;
+            rows[row].n_chunks = row_split(t_end - t0, L.chunk).count();
+            slot += rows[row].n_chunks;
             unit += t_end - t0;
         }
     }
-    if (nch != L.n_chunks || unit != L.n_units) return fail(FF_ERR_ARG, "internal: tile table size mismatch");
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int k = 0; k < n_sys; ++k) {
+            const SysInfo& si = sys[k];
+            for (int row = si.row0; row < si.row0 + si.nb; ++row) {
+                const RowInfo& ri = rows[row];
+                const int t_end = si.aoff / kTile + si.np / kTile;
+                const RowSplit sp = row_split(t_end - ri.t0, L.chunk);
+                int t = ri.t0, q = ri.chunk_start;
+                auto emit = [&](int len, int in_pass) {
+                    if (in_pass == pass) {
+                        ChunkInfo& c = chunks[nch++];
+                        c.row = row;
+                        c.t_begin = t;
+                        c.t_end = t + len;
+                        c.unit_base = ri.unit_start + (t - ri.t0);
+                        c.sys = k;
+                        c.slot = q;
+                    }
+                    t += len;
+                    ++q;
+                };
+                for (int i = 0; i < sp.full; ++i) emit(L.chunk, L.chunk == 1 ? 2 : 0);
+                if (sp.rem > 0) emit(sp.rem, sp.rem == 1 ? 2 : 1);
+                for (int i = 0; i < sp.tail; ++i) emit(1, 2);
+                if (t != t_end || q != ri.chunk_start + ri.n_chunks)
+                    return fail(FF_ERR_ARG, "internal: chunk split mismatch");
+            }
+        }
+    }
+    if (nch != L.n_chunks || slot != L.n_chunks || unit != L.n_units)
+        return fail(FF_ERR_ARG, "internal: tile table size mismatch");
     // bonded topology (local atom indices) and parameters
     int* bond = at<int>(img, L.off_bond);
     double* bondp = at<double>(img, L.off_bondp);

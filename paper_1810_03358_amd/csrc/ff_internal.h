@@ -172,17 +172,26 @@ constexpr TileConfig kTileConfigs[] = {
 constexpr int kNumTileConfigs = sizeof(kTileConfigs) / sizeof(kTileConfigs[0]);
 
 // ------------------------------------------------------------- tile tables
+// The chunk table is in launch order: every chunk of the full length first,
+// then the shorter ones, so that the last workgroups of a launch are the
+// shortest.  With chunks longer than one j-tile, the last 1/kTailDiv of each
+// I-block's j-tiles (at least one) go to one-tile chunks, which end the
+// launch.  A chunk's `slot` numbers it within its I-block in j order (the
+// I-block's chunks hold consecutive slots): the slot indexes its i-side
+// partial row and its energy share.
+constexpr int kTailDiv = 16;
 struct ChunkInfo {        // one workgroup of the pair kernel
     int32_t row;          // I-block index (global)
     int32_t t_begin, t_end;   // j-tiles [t_begin, t_end) (global)
     int32_t unit_base;    // index of unit (row, t_begin) in the Fj partial array
     int32_t sys;          // system the chunk belongs to
-    int32_t pad_[3];
+    int32_t slot;         // i-side partial row and energy share of the chunk
+    int32_t pad_[2];
 };
 struct RowInfo {          // one I-block
     int32_t unit_start;   // unit index of (row, t0)
     int32_t t0;           // first j-tile (diagonal)
-    int32_t chunk_start;
+    int32_t chunk_start;  // slot of its first chunk
     int32_t n_chunks;
 };
 

@@ -485,13 +485,13 @@ k_pair32(Args a) {
     }
     // FP32 mode stores its partial sums in single precision (they are FP32
     // tile sums already); the finalize adds them up in FP64
-    float* pi = at<float>(a.ws, L.off_pi) + (size_t)wg * B * 3;
+    float* pi = at<float>(a.ws, L.off_pi) + (size_t)ch.slot * B * 3;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int il = wave * 64 * IPL + k * 64 + lane;
         pi[3 * il] = (float)gx[k]; pi[3 * il + 1] = (float)gy[k]; pi[3 * il + 2] = (float)gz[k];
     }
-    block_energy_store<WAVES>(e64, at<double>(a.ws, L.off_ep) + wg);
+    block_energy_store<WAVES>(e64, at<double>(a.ws, L.off_ep) + ch.slot);
 }
 
 // ---------------------------------------------------------------- FP64 pairs
@@ -630,13 +630,13 @@ __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
             pj[0] = sx; pj[1] = sy; pj[2] = sz;
         }
     }
-    double* pi = at<double>(a.ws, L.off_pi) + (size_t)wg * B * 3;
+    double* pi = at<double>(a.ws, L.off_pi) + (size_t)ch.slot * B * 3;
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         const int il = wave * 64 * IPL + k * 64 + lane;
         pi[3 * il] = gx[k]; pi[3 * il + 1] = gy[k]; pi[3 * il + 2] = gz[k];
     }
-    block_energy_store<WAVES>(elj * (1.0 / 12.0) + ecs, at<double>(a.ws, L.off_ep) + wg);
+    block_energy_store<WAVES>(elj * (1.0 / 12.0) + ecs, at<double>(a.ws, L.off_ep) + ch.slot);
 }
 
 // The FP64 kernel walks the chunks with a grid stride: in FP32 mode (and in
