@@ -32,7 +32,9 @@ PEAK_FP64_TFLOPS = 78.6
 SCALAR_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
-PAIR_SOURCES = ["paper_1810_03358_amd/csrc/ff_pair.hip", "paper_1810_03358_amd/csrc/ff_internal.h"]
+# the pair kernel and the host code that lays out its chunk tables (both decide its traffic)
+PAIR_SOURCES = ["paper_1810_03358_amd/csrc/ff_pair.hip", "paper_1810_03358_amd/csrc/ff_internal.h",
+                "paper_1810_03358_amd/csrc/ff_api.hip"]
 
 
 def measured_traffic(workload: str, precision: str):
@@ -54,7 +56,7 @@ def measured_traffic(workload: str, precision: str):
     h = hashlib.sha256()
     for f in PAIR_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if fields.get("source_sha256 (ff_pair.hip + ff_internal.h at measurement)") != h.hexdigest():
+    if fields.get("source_sha256 (ff_pair.hip + ff_internal.h + ff_api.hip at measurement)") != h.hexdigest():
         return None
     return float(fields["traffic_bytes_per_launch"])
 

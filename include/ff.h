@@ -175,11 +175,13 @@ int32_t ff_batch_size(const ff_ctx *ctx);
 
 /* Tiling of the pair kernel.  The pair matrix of each system is cut into
  * I-blocks of `block` atoms against j-tiles of 64 atoms, and one workgroup
- * walks `chunk` consecutive j-tiles of one I-block; with chunk > 1 the last
- * sixteenth of each I-block's j-tiles (at least one) goes to one-tile chunks
- * that end the launch, so that it drains on short workgroups.  A tile
- * configuration fixes the block size and the wavefronts and i-atoms per lane
- * of the FP32 and FP64 kernels.  ff_create / ff_create_batch choose one from the system sizes; the
+ * walks a chunk of consecutive j-tiles of one I-block: `chunk` tiles in the
+ * FP32 kernel, `chunk64` in the FP64 kernel (each has its own chunk table).
+ * With chunks longer than one tile, the last sixteenth of each I-block's
+ * j-tiles (at least one) goes to one-tile chunks that end the launch, so that
+ * it drains on short workgroups.  A tile configuration fixes the block size
+ * and the wavefronts and i-atoms per lane of the FP32 and FP64 kernels.
+ * ff_create / ff_create_batch choose one from the system sizes; the
  * functions below name one explicitly.  The tiling changes only speed and the
  * summation order of the pair partials (results agree to rounding). */
 int32_t ff_num_tile_configs(void);
@@ -188,24 +190,26 @@ int32_t ff_num_tile_configs(void);
 ff_status ff_tile_config_info(int32_t cfg, int32_t *block, int32_t *waves32, int32_t *ipl32,
                               int32_t *waves64, int32_t *ipl64);
 /* Workspace bytes and context creation with an explicit configuration and
- * chunk length (1..4096); 0 / FF_ERR_ARG on invalid input. */
+ * chunk lengths (1..4096; chunk64 = 0 takes `chunk` for both kernels);
+ * 0 / FF_ERR_ARG on invalid input. */
 size_t ff_workspace_bytes_tiled(const ff_system *systems, int32_t n_sys, int32_t m_max,
-                                int32_t tile_config, int32_t chunk);
+                                int32_t tile_config, int32_t chunk, int32_t chunk64);
 ff_status ff_create_tiled(const ff_system *systems, int32_t n_sys, void *workspace,
                           size_t workspace_bytes, int32_t m_max, int32_t tile_config, int32_t chunk,
-                          void *stream, ff_ctx **out);
-/* Tiling of an existing context. */
-ff_status ff_get_tiling(const ff_ctx *ctx, int32_t *tile_config, int32_t *chunk);
+                          int32_t chunk64, void *stream, ff_ctx **out);
+/* Tiling of an existing context; any output may be NULL. */
+ff_status ff_get_tiling(const ff_ctx *ctx, int32_t *tile_config, int32_t *chunk, int32_t *chunk64);
 
 /* Autotuner: for every tile configuration and chunk length in {1, 2, 4, 8,
- * 16} whose layout fits, builds a temporary context for the systems in
+ * 16} (the same for both kernels) whose layout fits, builds a temporary context for the systems in
  * `workspace` (device, 256-byte aligned, overwritten), times `reps`
  * back-to-back energy+gradient evaluations at xyz (device, concatenated
  * [n][3]) in `precision` with HIP events on `stream`, and returns the fastest
  * configuration and its mean time per evaluation in ms.  Configurations that
  * do not fit the workspace are skipped (FF_ERR_WORKSPACE if none fits);
  * ff_autotune_workspace_bytes gives the size that fits all of them.  Blocks
- * until done.  The result is then passed to ff_create_tiled. */
+ * until done.  The result is then passed to ff_create_tiled (as chunk and
+ * chunk64, or as the chunk of the tuned precision only). */
 size_t ff_autotune_workspace_bytes(const ff_system *systems, int32_t n_sys);
 ff_status ff_autotune(const ff_system *systems, int32_t n_sys, const double *xyz, void *workspace,
                       size_t workspace_bytes, int32_t precision, int32_t reps, void *stream,

@@ -151,8 +151,11 @@ class Context:
     together; coordinates are then concatenated in list order)."""
 
     def __init__(self, system, m_max: int = 10, device="cuda", stream=None, tiling=None):
-        """``tiling`` = (tile_config, chunk) names the pair-kernel tiling
-        (e.g. from :func:`autotune`); None lets the library choose."""
+        """``tiling`` = (tile_config, chunk) or (tile_config, chunk,
+        chunk64) names the pair-kernel tiling (chunk64: the FP64 kernel's
+        chunk length, else `chunk`; e.g. from :func:`autotune`); None lets
+        the library choose.  ``self.tiling`` is the (tile_config, chunk,
+        chunk64) in use."""
         lib = N.load()
         self.is_batch = isinstance(system, (list, tuple))
         systems = list(system) if self.is_batch else [system]
@@ -166,8 +169,11 @@ class Context:
         if tiling is None:
             nbytes = int(lib.ff_workspace_bytes_batch(self._sys_array, self.n_sys, m_max))
         else:
-            nbytes = int(lib.ff_workspace_bytes_tiled(self._sys_array, self.n_sys, m_max, int(tiling[0]),
-                                                      int(tiling[1])))
+            tiling = tuple(int(v) for v in tiling)
+            if len(tiling) not in (2, 3):
+                raise ValueError("tiling must be (tile_config, chunk) or (tile_config, chunk, chunk64)")
+            tiling = tiling if len(tiling) == 3 else tiling + (tiling[1],)
+            nbytes = int(lib.ff_workspace_bytes_tiled(self._sys_array, self.n_sys, m_max, *tiling))
         if nbytes == 0:
             raise FFError(FF_ERR_ARG, "ff_workspace_bytes")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -179,13 +185,13 @@ class Context:
                                        _stream_ptr(stream), C.byref(ctx)), "ff_create_batch")
         else:
             _check(lib.ff_create_tiled(self._sys_array, self.n_sys, C.c_void_p(self._ws_ptr), nbytes, m_max,
-                                       int(tiling[0]), int(tiling[1]), _stream_ptr(stream), C.byref(ctx)),
+                                       *tiling, _stream_ptr(stream), C.byref(ctx)),
                    "ff_create_tiled")
         self._ctx = ctx
         self.m_max = m_max
-        cfg, ch = C.c_int32(), C.c_int32()
-        _check(lib.ff_get_tiling(self._ctx, C.byref(cfg), C.byref(ch)), "ff_get_tiling")
-        self.tiling = (cfg.value, ch.value)
+        cfg, ch, ch64 = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib.ff_get_tiling(self._ctx, C.byref(cfg), C.byref(ch), C.byref(ch64)), "ff_get_tiling")
+        self.tiling = (cfg.value, ch.value, ch64.value)
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -103,12 +103,13 @@ def load():
     lib.ff_num_tile_configs.restype = C.c_int32
     lib.ff_tile_config_info.argtypes = [C.c_int32, _ip, _ip, _ip, _ip, _ip]
     lib.ff_tile_config_info.restype = C.c_int
-    lib.ff_workspace_bytes_tiled.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    lib.ff_workspace_bytes_tiled.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                             C.c_int32]
     lib.ff_workspace_bytes_tiled.restype = C.c_size_t
     lib.ff_create_tiled.argtypes = [C.POINTER(FFSystem), C.c_int32, C.c_void_p, C.c_size_t, C.c_int32,
-                                    C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+                                    C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.ff_create_tiled.restype = C.c_int
-    lib.ff_get_tiling.argtypes = [C.c_void_p, _ip, _ip]
+    lib.ff_get_tiling.argtypes = [C.c_void_p, _ip, _ip, _ip]
     lib.ff_get_tiling.restype = C.c_int
     lib.ff_autotune_workspace_bytes.argtypes = [C.POINTER(FFSystem), C.c_int32]
     lib.ff_autotune_workspace_bytes.restype = C.c_size_t

@@ -142,7 +142,8 @@ static RowSplit row_split(int T, int c) {
 }
 
 static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, SysInfo* sys, FarTmp& ft,
-                        int32_t cfg_req = -1, int32_t chunk_req = 0, bool energy_only = false) {
+                        int32_t cfg_req = -1, int32_t chunk_req = 0, int32_t chunk64_req = 0,
+                        bool energy_only = false) {
     std::memset(&L, 0, sizeof L);
     if (!s || n_sys < 1 || !sys) return false;
     if (m_max < 0 || m_max > kMaxM) return false;
@@ -157,24 +158,33 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     if (ft.cap < far_capacity(s, n_sys)) return false;
     L.n_sys = n_sys;
     // defaults from sweeps of whole FP32 and FP64 evaluations on MI355X
-    // (2,500 to 50,000 atoms, every configuration x chunks of 1, 2, 4):
-    // batches and small systems use 64-atom blocks; up to 12,288 atoms
-    // 256-atom blocks with one atom per lane and one j-tile per workgroup
-    // (enough workgroups to fill the chip: 0.085 instead of 0.105 ms per FP32
-    // evaluation at 10k atoms); above, two atoms per lane in FP32 and four in
-    // FP64, with chunks of two j-tiles from 32,768 atoms on
-    if (n_sys > 1) { L.cfg = 0; L.chunk = 4; }
-    else if (n_max <= 2048) { L.cfg = 0; L.chunk = 2; }
-    else if (n_max < 12288) { L.cfg = 1; L.chunk = 1; }
-    else if (n_max < 32768) { L.cfg = 8; L.chunk = 1; }
-    else { L.cfg = 8; L.chunk = 2; }
+    // (2,048 to 50,000 atoms, configurations x chunk lengths 1 to 16, per
+    // precision): batches and systems up to 6,144 atoms use 64-atom blocks;
+    // up to 12,288 atoms 256-atom blocks with one atom per lane (enough
+    // workgroups to fill the chip); above, two atoms per lane in FP32 and four
+    // in FP64.  The FP64 kernel, with fewer and longer-lived wavefronts,
+    // gains from longer chunks as the system grows (two j-tiles from 20,000
+    // atoms, four from 32,768, eight from 45,000 on: 1.49 instead of 1.55 ms
+    // per FP64 evaluation at 50k atoms), the FP32 kernel from two j-tiles
+    // only above 32,768 atoms
+    auto pick = [&](int cfg, int c32, int c64) { L.cfg = cfg; L.chunk[0] = c32; L.chunk[1] = c64; };
+    if (n_sys > 1) pick(0, 4, 4);
+    else if (n_max <= 6144) pick(0, 1, 1);
+    else if (n_max < 12288) pick(1, 1, 2);
+    else if (n_max < 20000) pick(8, 1, 1);
+    else if (n_max < 32768) pick(8, 1, 2);
+    else if (n_max < 45000) pick(8, 2, 4);
+    else pick(8, 2, 8);
     if (cfg_req >= 0) {
-        if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk) return false;
-        L.cfg = cfg_req;
-        L.chunk = chunk_req;
+        if (chunk64_req == 0) chunk64_req = chunk_req;
+        if (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk || chunk64_req < 1 ||
+            chunk64_req > kMaxChunk)
+            return false;
+        pick(cfg_req, chunk_req, chunk64_req);
     }
     L.block = kTileConfigs[L.cfg].block;
-    int aoff = 0, uoff = 0, units = 0, chunks = 0, nbd = 0, nag = 0, ndh = 0, ebo = 0;
+    int aoff = 0, uoff = 0, units = 0, nbd = 0, nag = 0, ndh = 0, ebo = 0;
+    int chunks[2] = {0, 0};
     size_t red = 0;
     L.acc_rows = std::max(1, m_max + 1);
     for (int k = 0; k < n_sys; ++k) {
@@ -186,14 +196,15 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
         si.uoff = uoff;
         si.row0 = aoff / L.block;
         si.nb = si.np / L.block;
-        si.chunk0 = chunks;
+        si.chunk0[0] = chunks[0];
+        si.chunk0[1] = chunks[1];
         const int nt = si.np / kTile;
         for (int b = 0; b < si.nb; ++b) {
             const int t0 = b * L.block / kTile;
             units += nt - t0;
-            chunks += row_split(nt - t0, L.chunk).count();
+            for (int p = 0; p < 2; ++p) chunks[p] += row_split(nt - t0, L.chunk[p]).count();
         }
-        si.n_chunks = chunks - si.chunk0;
+        for (int p = 0; p < 2; ++p) si.n_chunks[p] = chunks[p] - si.chunk0[p];
         si.n_bonds = s[k].n_bonds;
         si.n_angles = s[k].n_angles;
         si.n_dihedrals = s[k].n_dihedrals;
@@ -222,7 +233,9 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.nb = aoff / L.block;
     L.nt = aoff / kTile;
     L.n_units = units;
-    L.n_chunks = chunks;
+    L.n_chunks[0] = chunks[0];
+    L.n_chunks[1] = chunks[1];
+    const size_t max_chunks = (size_t)std::max(chunks[0], chunks[1]);
     L.n_bonds = nbd;
     L.n_angles = nag;
     L.n_dihedrals = ndh;
@@ -252,7 +265,8 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.off_c6d = take(np * 8);
     L.off_qd = take(np * 8);
     L.off_excl = take(np * 8);
-    L.off_chunks = take((size_t)L.n_chunks * sizeof(ChunkInfo));
+    L.off_chunks[0] = take((size_t)L.n_chunks[0] * sizeof(ChunkInfo));
+    L.off_chunks[1] = take((size_t)L.n_chunks[1] * sizeof(ChunkInfo));
     L.off_rows = take((size_t)L.nb * sizeof(RowInfo));
     L.off_bond = take((size_t)L.n_bonds * 8);
     L.off_bondp = take((size_t)L.n_bonds * 16);
@@ -272,9 +286,9 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     // written by the kernels
     L.off_batch = take(sizeof(BatchState));
     L.off_ctl = take((size_t)n_sys * L.ctl_stride);
-    L.off_pi = take((size_t)L.n_chunks * L.block * 3 * 8);
+    L.off_pi = take(max_chunks * L.block * 3 * 8);
     L.off_pj = take((size_t)L.n_units * kTile * 3 * 8);
-    L.off_ep = take((size_t)L.n_chunks * 8);
+    L.off_ep = take(max_chunks * 8);
     L.off_fb = take((size_t)L.n_terms_slots * 24);
     L.off_eb = take((size_t)L.n_bonded_blocks * 8);
     L.off_red = take(red * 8);
@@ -293,7 +307,7 @@ struct LayoutHost {
 };
 
 static bool layout_heap(const ff_system* s, int32_t n_sys, int32_t m_max, Layout& L, LayoutHost& h,
-                        int32_t cfg_req = -1, int32_t chunk_req = 0) {
+                        int32_t cfg_req = -1, int32_t chunk_req = 0, int32_t chunk64_req = 0) {
     std::memset(&L, 0, sizeof L);
     if (!s || n_sys < 1) return false;
     const size_t cap = far_capacity(s, n_sys);
@@ -301,7 +315,7 @@ static bool layout_heap(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     h.pairs.assign(cap, FarPair{0, 0});
     h.keys.assign(cap, 0);
     h.ft = FarTmp{h.pairs.data(), h.keys.data(), cap};
-    return make_layout(s, n_sys, m_max, L, h.sys.data(), h.ft, cfg_req, chunk_req);
+    return make_layout(s, n_sys, m_max, L, h.sys.data(), h.ft, cfg_req, chunk_req, chunk64_req);
 }
 
 static double* trace_buffer(const ff_ctx* c) {
@@ -387,12 +401,11 @@ static ff_status pack_static(const ff_system* systems, int32_t n_sys, const Layo
             qf[g] = (float)qd[g];
         }
     }
-    // tile tables (global I-block and j-tile indices): rows, then the chunks
-    // in launch order (three passes: full-length chunks, shorter remainders,
-    // one-tile chunks; each pass row by row)
-    ChunkInfo* chunks = at<ChunkInfo>(img, L.off_chunks);
+    // tile tables (global I-block and j-tile indices): rows, then each chunk
+    // table in launch order (three passes: full-length chunks, shorter
+    // remainders, one-tile chunks; each pass row by row)
     RowInfo* rows = at<RowInfo>(img, L.off_rows);
-    int unit = 0, slot = 0, nch = 0;
+    int unit = 0, slot[2] = {0, 0};
     for (int k = 0; k < n_sys; ++k) {
         const SysInfo& si = sys[k];
         const int tile0 = si.aoff / kTile, nt = si.np / kTile;
@@ -401,43 +414,51 @@ static ff_status pack_static(const ff_system* systems, int32_t n_sys, const Layo
             const int t0 = tile0 + b * L.block / kTile, t_end = tile0 + nt;
             rows[row].unit_start = unit;
             rows[row].t0 = t0;
-            rows[row].chunk_start = slot;
-            rows[row].n_chunks = row_split(t_end - t0, L.chunk).count();
-            slot += rows[row].n_chunks;
+            for (int p = 0; p < 2; ++p) {
+                rows[row].chunk_start[p] = slot[p];
+                rows[row].n_chunks[p] = row_split(t_end - t0, L.chunk[p]).count();
+                slot[p] += rows[row].n_chunks[p];
+            }
             unit += t_end - t0;
         }
     }
-    for (int pass = 0; pass < 3; ++pass) {
-        for (int k = 0; k < n_sys; ++k) {
-            const SysInfo& si = sys[k];
-            for (int row = si.row0; row < si.row0 + si.nb; ++row) {
-                const RowInfo& ri = rows[row];
+    if (slot[0] != L.n_chunks[0] || slot[1] != L.n_chunks[1] || unit != L.n_units)
+        return fail(FF_ERR_ARG, "internal: tile table size mismatch");
+    for (int p = 0; p < 2; ++p) {
+        ChunkInfo* chunks = at<ChunkInfo>(img, L.off_chunks[p]);
+        const int c_len = L.chunk[p];
+        int nch = 0;
+        for (int pass = 0; pass < 3; ++pass) {
+            for (int k = 0; k < n_sys; ++k) {
+                const SysInfo& si = sys[k];
                 const int t_end = si.aoff / kTile + si.np / kTile;
-                const RowSplit sp = row_split(t_end - ri.t0, L.chunk);
-                int t = ri.t0, q = ri.chunk_start;
-                auto emit = [&](int len, int in_pass) {
-                    if (in_pass == pass) {
-                        ChunkInfo& c = chunks[nch++];
-                        c.row = row;
-                        c.t_begin = t;
-                        c.t_end = t + len;
-                        c.unit_base = ri.unit_start + (t - ri.t0);
-                        c.sys = k;
-                        c.slot = q;
-                    }
-                    t += len;
-                    ++q;
-                };
-                for (int i = 0; i < sp.full; ++i) emit(L.chunk, L.chunk == 1 ? 2 : 0);
-                if (sp.rem > 0) emit(sp.rem, sp.rem == 1 ? 2 : 1);
-                for (int i = 0; i < sp.tail; ++i) emit(1, 2);
-                if (t != t_end || q != ri.chunk_start + ri.n_chunks)
-                    return fail(FF_ERR_ARG, "internal: chunk split mismatch");
+                for (int row = si.row0; row < si.row0 + si.nb; ++row) {
+                    const RowInfo& ri = rows[row];
+                    const RowSplit sp = row_split(t_end - ri.t0, c_len);
+                    int t = ri.t0, q = ri.chunk_start[p];
+                    auto emit = [&](int len, int in_pass) {
+                        if (in_pass == pass) {
+                            ChunkInfo& c = chunks[nch++];
+                            c.row = row;
+                            c.t_begin = t;
+                            c.t_end = t + len;
+                            c.unit_base = ri.unit_start + (t - ri.t0);
+                            c.sys = k;
+                            c.slot = q;
+                        }
+                        t += len;
+                        ++q;
+                    };
+                    for (int i = 0; i < sp.full; ++i) emit(c_len, c_len == 1 ? 2 : 0);
+                    if (sp.rem > 0) emit(sp.rem, sp.rem == 1 ? 2 : 1);
+                    for (int i = 0; i < sp.tail; ++i) emit(1, 2);
+                    if (t != t_end || q != ri.chunk_start[p] + ri.n_chunks[p])
+                        return fail(FF_ERR_ARG, "internal: chunk split mismatch");
+                }
             }
         }
+        if (nch != L.n_chunks[p]) return fail(FF_ERR_ARG, "internal: chunk table size mismatch");
     }
-    if (nch != L.n_chunks || slot != L.n_chunks || unit != L.n_units)
-        return fail(FF_ERR_ARG, "internal: tile table size mismatch");
     // bonded topology (local atom indices) and parameters
     int* bond = at<int>(img, L.off_bond);
     double* bondp = at<double>(img, L.off_bondp);
@@ -550,10 +571,11 @@ size_t ff_workspace_bytes_batch(const ff_system* sys, int32_t n_sys, int32_t m_m
 }
 
 size_t ff_workspace_bytes_tiled(const ff_system* sys, int32_t n_sys, int32_t m_max, int32_t tile_config,
-                                int32_t chunk) {
+                                int32_t chunk, int32_t chunk64) {
     Layout L;
     LayoutHost h;
-    if (tile_config < 0 || !layout_heap(sys, n_sys, m_max, L, h, tile_config, chunk)) return 0;
+    if (tile_config < 0 || chunk64 < 0 || !layout_heap(sys, n_sys, m_max, L, h, tile_config, chunk, chunk64))
+        return 0;
     return L.total;
 }
 
@@ -602,7 +624,8 @@ const char* ff_last_error(void) { return g_err; }
 int32_t ff_batch_size(const ff_ctx* c) { return c ? c->L.n_sys : 0; }
 
 static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes,
-                             int32_t m_max, int32_t cfg_req, int32_t chunk_req, void* stream, ff_ctx** out) {
+                             int32_t m_max, int32_t cfg_req, int32_t chunk_req, int32_t chunk64_req, void* stream,
+                             ff_ctx** out) {
     clear_error();
     if (!out) return fail(FF_ERR_ARG, "out is null");
     *out = nullptr;
@@ -612,10 +635,12 @@ static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* work
     if (m_max < 0 || m_max > kMaxM) return fail(FF_ERR_ARG, "m_max must be in [0, %d]", kMaxM);
     Layout L;
     LayoutHost h;
-    if (cfg_req >= 0 && (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk))
-        return fail(FF_ERR_ARG, "tile configuration %d / chunk %d outside [0, %d) / [1, %d]", cfg_req, chunk_req,
-                    kNumTileConfigs, kMaxChunk);
-    if (!layout_heap(systems, n_sys, m_max, L, h, cfg_req, chunk_req)) return fail(FF_ERR_ARG, "invalid sizes");
+    if (cfg_req >= 0 && (cfg_req >= kNumTileConfigs || chunk_req < 1 || chunk_req > kMaxChunk ||
+                         chunk64_req < 0 || chunk64_req > kMaxChunk))
+        return fail(FF_ERR_ARG, "tile configuration %d / chunks %d, %d outside [0, %d) / [1, %d] (chunk64 0: = chunk)",
+                    cfg_req, chunk_req, chunk64_req, kNumTileConfigs, kMaxChunk);
+    if (!layout_heap(systems, n_sys, m_max, L, h, cfg_req, chunk_req, chunk64_req))
+        return fail(FF_ERR_ARG, "invalid sizes");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(FF_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
     if (ws_bytes < L.total) return fail(FF_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
     std::vector<char> img(L.static_end);
@@ -656,26 +681,28 @@ static ff_status create_impl(const ff_system* systems, int32_t n_sys, void* work
 
 ff_status ff_create_batch(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes, int32_t m_max,
                           void* stream, ff_ctx** out) {
-    return create_impl(systems, n_sys, workspace, ws_bytes, m_max, -1, 0, stream, out);
+    return create_impl(systems, n_sys, workspace, ws_bytes, m_max, -1, 0, 0, stream, out);
 }
 
 ff_status ff_create_tiled(const ff_system* systems, int32_t n_sys, void* workspace, size_t ws_bytes,
-                          int32_t m_max, int32_t tile_config, int32_t chunk, void* stream, ff_ctx** out) {
+                          int32_t m_max, int32_t tile_config, int32_t chunk, int32_t chunk64, void* stream,
+                          ff_ctx** out) {
     if (tile_config < 0) {
         fail(FF_ERR_ARG, "tile_config must be >= 0 (ff_create_batch picks one itself)");
         if (out) *out = nullptr;
         return FF_ERR_ARG;
     }
-    return create_impl(systems, n_sys, workspace, ws_bytes, m_max, tile_config, chunk, stream, out);
+    return create_impl(systems, n_sys, workspace, ws_bytes, m_max, tile_config, chunk, chunk64, stream, out);
 }
 
-ff_status ff_get_tiling(const ff_ctx* c, int32_t* tile_config, int32_t* chunk) {
+ff_status ff_get_tiling(const ff_ctx* c, int32_t* tile_config, int32_t* chunk, int32_t* chunk64) {
     if (!c) {
         fail(FF_ERR_ARG, "context is null");
         return FF_ERR_ARG;
     }
     if (tile_config) *tile_config = c->L.cfg;
-    if (chunk) *chunk = c->L.chunk;
+    if (chunk) *chunk = c->L.chunk[0];
+    if (chunk64) *chunk64 = c->L.chunk[1];
     return FF_OK;
 }
 
@@ -721,7 +748,7 @@ ff_status ff_autotune(const ff_system* systems, int32_t n_sys, const double* xyz
             LayoutHost h;
             if (!layout_heap(systems, n_sys, 0, L, h, cfg, ch) || L.total > usable) continue;
             ff_ctx* c = nullptr;
-            ff_status s = create_impl(systems, n_sys, workspace, usable, 0, cfg, ch, stream, &c);
+            ff_status s = create_impl(systems, n_sys, workspace, usable, 0, cfg, ch, ch, stream, &c);
             if (s) { result = s; break; }
             double* eo = e_out;
             hipError_t e = ff_energy_grad(c, xyz, eo, nullptr, precision, st) == FF_OK ? hipSuccess : hipErrorUnknown;
@@ -795,7 +822,7 @@ ff_status ff_energy_grad_noalloc(const ff_system* sys, const double* xyz, double
     FarTmp ft{reinterpret_cast<FarPair*>(tmp), reinterpret_cast<long long*>(tmp + cap * sizeof(FarPair)), cap};
     Layout L;
     SysInfo si;
-    if (!make_layout(sys, 1, 0, L, &si, ft, -1, 0, true)) return fail(FF_ERR_ARG, "invalid sizes");
+    if (!make_layout(sys, 1, 0, L, &si, ft, -1, 0, 0, true)) return fail(FF_ERR_ARG, "invalid sizes");
     if (L.total > FF_NOALLOC_SCRATCH_BYTES || L.static_end > sizeof g_stage - tmp_bytes)
         return fail(FF_ERR_UNSUPPORTED, "a system of %d atoms needs %zu bytes of device scratch; "
                     "ff_energy_grad_noalloc has %zu (use a context)", sys->n_atoms, L.total,

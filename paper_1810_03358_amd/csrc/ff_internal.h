@@ -156,7 +156,9 @@ struct Ctl {
 // ------------------------------------------------------- pair tile configs
 // I-block of `block` atoms; the FP32 and FP64 kernels split it into
 // waves x 64 lanes x ipl atoms per lane.  Both precisions of one
-// configuration share the block size, hence one chunk table.
+// configuration share the block size, hence the rows and units of the pair
+// matrix; each precision has its own chunk length and chunk table (index 0:
+// FP32 kernel, 1: FP64 kernel).
 struct TileConfig { int block, waves32, ipl32, waves64, ipl64; };
 constexpr TileConfig kTileConfigs[] = {
     {64, 1, 1, 1, 1},     // 0
@@ -191,8 +193,8 @@ struct ChunkInfo {        // one workgroup of the pair kernel
 struct RowInfo {          // one I-block
     int32_t unit_start;   // unit index of (row, t0)
     int32_t t0;           // first j-tile (diagonal)
-    int32_t chunk_start;  // slot of its first chunk
-    int32_t n_chunks;
+    int32_t chunk_start[2];   // slot of its first chunk, per chunk table
+    int32_t n_chunks[2];
 };
 
 // One system of a batch.  Atom indices in its topology are local (0..n-1);
@@ -203,7 +205,7 @@ struct SysInfo {
     int32_t aoff;         // first padded atom (global); vectors start at 3*aoff
     int32_t uoff;         // first atom in the caller's concatenated [sum n][3] arrays
     int32_t row0, nb;     // first I-block (global) and count
-    int32_t chunk0, n_chunks;
+    int32_t chunk0[2], n_chunks[2];   // first slot and chunks, per chunk table
     int32_t n_bonds, n_angles, n_dihedrals;
     int32_t bond0, angle0, dih0;   // first bond / angle / torsion in the batch-wide arrays
     int32_t bonded_blocks, eb0;
@@ -214,7 +216,8 @@ struct SysInfo {
 
 struct Layout {
     int32_t n_sys;
-    int32_t n, np, nb, nt, block, chunk, n_chunks, n_units;   // n, np: totals over the batch
+    int32_t n, np, nb, nt, block, n_units;   // n, np: totals over the batch
+    int32_t chunk[2], n_chunks[2];        // chunk length and chunks: [0] FP32 kernel, [1] FP64 kernel
     int32_t n_bonds, n_angles, n_dihedrals, n_terms_slots, n_bonded_blocks;
     int32_t n_far_units;      // units holding an excluded pair more than kExclWindow apart
     int32_t n_fin_blocks;
@@ -228,7 +231,7 @@ struct Layout {
     // byte offsets
     size_t off_batch, off_sys;
     size_t off_ctl, off_c12, off_c6, off_q, off_c12d, off_c6d, off_qd, off_excl;
-    size_t off_chunks, off_rows, off_pi, off_pj, off_ep;
+    size_t off_chunks[2], off_rows, off_pi, off_pj, off_ep;   // i-side partials and energies: max over the tables
     size_t off_bond, off_bondp, off_angle, off_anglep, off_dih, off_dihp;
     size_t off_fb, off_eb, off_inc_start, off_inc;
     size_t off_red, off_vec;

@@ -169,7 +169,8 @@ __device__ __forceinline__ void gather_tile(const Args& a, const SysInfo& si, in
     const int row0 = si.row0;
     const RowInfo ri = R[row];
     const int il0 = t * kTile - row * L.block;
-    const int n_i = ri.n_chunks, nseg = n_i + row - row0 + 1;
+    constexpr int tab = sizeof(T) == 4 ? 0 : 1;          // chunk table of the kernel that wrote Pi
+    const int n_i = ri.n_chunks[tab], nseg = n_i + row - row0 + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int kWaves = kFinBlock / 64;
     // Units of a system are numbered row by row, local row r holding tiles
@@ -179,7 +180,7 @@ __device__ __forceinline__ void gather_tile(const Args& a, const SysInfo& si, in
     const long long nt = si.np / kTile, b64 = L.block / kTile;
     const long long tl = t - si.aoff / kTile;
     auto seg = [&](int sg) -> const T* {
-        if (sg < n_i) return Pi + ((size_t)(ri.chunk_start + sg) * L.block + il0) * 3;
+        if (sg < n_i) return Pi + ((size_t)(ri.chunk_start[tab] + sg) * L.block + il0) * 3;
         const long long r = sg - n_i;
         const long long unit = u0 + r * nt - b64 * r * (r - 1) / 2 + (tl - r * b64);
         return Pj + (size_t)unit * (3 * kTile);
@@ -289,9 +290,11 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Args a) {
     // this workgroup's share of the pair-workgroup and bonded-block energies
     {
         const int nb = si.fin_blocks, b = blk;
-        const double* ep = at<double>(a.ws, L.off_ep) + si.chunk0;
+        const int tab = p32 ? 0 : 1;                     // chunk table of the pair kernel that ran
+        const double* ep = at<double>(a.ws, L.off_ep) + si.chunk0[tab];
         const double* eb = at<double>(a.ws, L.off_eb) + si.eb0;
-        const int p0 = (int)((long long)si.n_chunks * b / nb), p1 = (int)((long long)si.n_chunks * (b + 1) / nb);
+        const int nc = si.n_chunks[tab];
+        const int p0 = (int)((long long)nc * b / nb), p1 = (int)((long long)nc * (b + 1) / nb);
         const int q0 = (int)((long long)si.bonded_blocks * b / nb), q1 = (int)((long long)si.bonded_blocks * (b + 1) / nb);
         double e = 0.0;
         for (int k = p0 + (int)threadIdx.x; k < p1; k += kFinBlock) e += ep[k];

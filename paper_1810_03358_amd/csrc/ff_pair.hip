@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 k_pair32(Args a) {
     const Layout& L = a.L;
     const int wg = blockIdx.x;
-    const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
+    const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks[0])[wg];
     if (!eval_active(a, ch.sys, 1)) return;
     const SysInfo si = sys_info(a)[ch.sys];
     const double* X = eval_coords(a, ch.sys, si);
@@ -555,7 +555,7 @@ __device__ __forceinline__ void tile64(const double4* __restrict__ s_xq, const d
 template <int WAVES, int IPL>
 __device__ __forceinline__ void pair64_chunk(const Args& a, int wg) {
     const Layout& L = a.L;
-    const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks)[wg];
+    const ChunkInfo ch = at<ChunkInfo>(a.ws, L.off_chunks[1])[wg];
     if (!eval_active(a, ch.sys, 0)) return;
     const SysInfo si = sys_info(a)[ch.sys];
     const double* X = eval_coords(a, ch.sys, si);
@@ -662,12 +662,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
         for (int s = threadIdx.x; s < a.L.n_sys && !any; s += blockDim.x) any = eval_active(a, s, 0) ? 1 : 0;
         if (!__syncthreads_or(any)) return;
     }
-    for (int wg = blockIdx.x; wg < a.L.n_chunks; wg += gridDim.x) pair64_chunk<WAVES, IPL>(a, wg);
+    for (int wg = blockIdx.x; wg < a.L.n_chunks[1]; wg += gridDim.x) pair64_chunk<WAVES, IPL>(a, wg);
 }
 
 // ------------------------------------------------------------- host launch
 // Tile configurations (index = Layout::cfg): I-block of B = 64 * waves * ipl
-// atoms.  Both precisions use the same B so that they share one chunk table.
+// atoms.  Both precisions use the same B (the same rows and units); each
+// walks its own chunk table.
 #define FF_PAIR_CASE(ID)                                                                           \
     case ID: {                                                                                     \
         constexpr TileConfig T = kTileConfigs[ID];                                                 \
@@ -682,7 +683,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_pair64(Args a) {
     }
 
 hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
-    const int grid = a.L.n_chunks;
+    const int grid = a.L.n_chunks[prec ? 0 : 1];
     switch (a.L.cfg) {
         FF_PAIR_CASE(0)
         FF_PAIR_CASE(1)

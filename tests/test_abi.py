@@ -130,13 +130,17 @@ def test_tile_configs_and_tiled_workspace():
     arr = (N.FFSystem * 1)(ff.HostSystem(s).c)
     for k in range(len(cfgs)):
         for chunk in (1, 4, 16):
-            b = lib.ff_workspace_bytes_tiled(arr, 1, 10, k, chunk)
+            b = lib.ff_workspace_bytes_tiled(arr, 1, 10, k, chunk, 0)
             assert b > 0 and b % 256 == 0
-    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, len(cfgs), 4) == 0
-    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 0) == 0
-    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 5000) == 0
+            # separate FP64 chunk length: its own chunk table, partial rows sized for the longer table
+            assert lib.ff_workspace_bytes_tiled(arr, 1, 10, k, chunk, 1) >= b
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, len(cfgs), 4, 0) == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 0, 0) == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 5000, 0) == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 4, 5000) == 0
+    assert lib.ff_workspace_bytes_tiled(arr, 1, 10, 0, 4, -1) == 0
     need = lib.ff_autotune_workspace_bytes(arr, 1)
-    assert need >= max(lib.ff_workspace_bytes_tiled(arr, 1, 0, k, c) for k in range(len(cfgs)) for c in (1, 16))
+    assert need >= max(lib.ff_workspace_bytes_tiled(arr, 1, 0, k, c, 0) for k in range(len(cfgs)) for c in (1, 16))
     assert lib.ff_tile_config_info(len(cfgs), None, None, None, None, None) == ff.FF_ERR_ARG
 
 
@@ -145,10 +149,11 @@ def test_create_tiled_rejects_bad_tiling_before_touching_the_device():
     s = chain_system(100, 3)
     arr = (N.FFSystem * 1)(ff.HostSystem(s).c)
     ctx = C.c_void_p()
-    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, -1, 4, None, C.byref(ctx)) == ff.FF_ERR_ARG
-    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 99, 4, None, C.byref(ctx)) == ff.FF_ERR_ARG
-    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 0, 0, None, C.byref(ctx)) == ff.FF_ERR_ARG
-    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1024, 10, 0, 4, None, C.byref(ctx)) == ff.FF_ERR_WORKSPACE
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, -1, 4, 0, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 99, 4, 0, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 0, 0, 0, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1 << 40, 10, 0, 4, 5000, None, C.byref(ctx)) == ff.FF_ERR_ARG
+    assert lib.ff_create_tiled(arr, 1, C.c_void_p(256), 1024, 10, 0, 4, 0, None, C.byref(ctx)) == ff.FF_ERR_WORKSPACE
 
 
 def test_energy_profile_rejects_bad_arguments_on_the_host():
@@ -170,8 +175,8 @@ def test_far_exclusions_are_accepted_and_sized():
     a = (N.FFSystem * 1)(ff.HostSystem(plain).c)
     b = (N.FFSystem * 1)(ff.HostSystem(linked).c)
     for cfg, block in enumerate(t[0] for t in ff.tile_configs()):
-        wa = lib.ff_workspace_bytes_tiled(a, 1, 10, cfg, 2)
-        wb = lib.ff_workspace_bytes_tiled(b, 1, 10, cfg, 2)
+        wa = lib.ff_workspace_bytes_tiled(a, 1, 10, cfg, 2, 0)
+        wb = lib.ff_workspace_bytes_tiled(b, 1, 10, cfg, 2, 0)
         assert wa > 0 and wb > wa
 
 

@@ -26,7 +26,8 @@ CONFIGS = list(range(len(ff.tile_configs())))
 
 def _run(s, x, prec, tiling):
     ctx = ff.Context(s, m_max=0, tiling=tiling)
-    assert ctx.tiling == tiling
+    expected = tuple(tiling) if len(tiling) == 3 else tuple(tiling) + (tiling[1],)
+    assert ctx.tiling == expected
     xt = torch.tensor(np.asarray(x).reshape(-1, 3), dtype=torch.float64, device="cuda")
     e, g = ctx.energy_grad(xt, prec)
     torch.cuda.synchronize()
@@ -43,14 +44,16 @@ def system():
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
-@pytest.mark.parametrize("chunk", [1, 3])
-def test_every_tiling_matches_the_oracle(system, cfg, chunk):
+@pytest.mark.parametrize("chunks", [(1, 1), (3, 3), (2, 5)])
+def test_every_tiling_matches_the_oracle(system, cfg, chunks):
+    """chunks = (FP32 kernel's, FP64 kernel's chunk length); lengths above one
+    also put each I-block's last j-tiles into one-tile chunks."""
     s, e_ref, g_ref, pair_force_sum = system
-    print(f"tiling cfg={cfg} chunk={chunk} n={s['n_atoms']}", flush=True)
-    e, g = _run(s, s["x"], "fp64", (cfg, chunk))
+    print(f"tiling cfg={cfg} chunks={chunks} n={s['n_atoms']}", flush=True)
+    e, g = _run(s, s["x"], "fp64", (cfg,) + chunks)
     assert abs(e - e_ref) <= 1e-11 * abs(e_ref)
     np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-11 * np.abs(g_ref).max())
-    e32, g32 = _run(s, s["x"], "fp32", (cfg, chunk))
+    e32, g32 = _run(s, s["x"], "fp32", (cfg,) + chunks)
     assert abs(e32 - e_ref) <= 1e-6 * abs(e_ref)
     bound = 2.0 ** -16 * pair_force_sum[:, None] + 1e-9 * np.abs(g_ref).max()
     assert np.all(np.abs(g32 - g_ref) <= bound), np.abs(g32 - g_ref).max()
@@ -83,10 +86,28 @@ def linked():
 def test_far_exclusions_match_the_oracle_for_every_tiling(linked, cfg):
     s, e_ref, g_ref, pair_force_sum = linked
     print(f"far exclusions cfg={cfg}", flush=True)
-    e, g = _run(s, s["x"], "fp64", (cfg, 2))
+    e, g = _run(s, s["x"], "fp64", (cfg, 2, 4))
     assert abs(e - e_ref) <= 1e-11 * abs(e_ref)
     np.testing.assert_allclose(g, g_ref, rtol=0, atol=1e-11 * np.abs(g_ref).max())
-    e32, g32 = _run(s, s["x"], "fp32", (cfg, 2))
+    e32, g32 = _run(s, s["x"], "fp32", (cfg, 2, 4))
     assert abs(e32 - e_ref) <= 1e-6 * abs(e_ref)
     bound = 2.0 ** -16 * pair_force_sum[:, None] + 1e-9 * np.abs(g_ref).max()
     assert np.all(np.abs(g32 - g_ref) <= bound), np.abs(g32 - g_ref).max()
+
+
+def test_fp32_mode_minimization_with_separate_chunk_tables():
+    """FP32 mode runs both pair kernels in one minimization (FP32 evaluations,
+    then the FP64 end game); with different chunk lengths each kernel walks
+    its own chunk table and the finalize reads the matching partial rows."""
+    s = chain_system(1100, 31)
+    print("fp32-mode minimize, tiling (4, 1, 3)", flush=True)
+    ctx = ff.Context(s, m_max=10, tiling=(4, 1, 3))
+    x = torch.tensor(s["x"], dtype=torch.float64, device="cuda")
+    r = ctx.minimize(x, "lbfgs", max_iter=400, precision="fp32", tol=1.0)
+    assert r["evals_fp64"] >= 1 and r["evals"] > r["evals_fp64"]
+    xs = x.cpu().numpy()
+    e_ref, g_ref = oracle.energy_grad(s, xs)
+    assert r["energy"] == pytest.approx(e_ref, rel=1e-9)
+    assert r["grad_inf"] == pytest.approx(np.abs(g_ref).max(), rel=1e-6)
+    e0, _ = oracle.energy_grad(s, s["x"])         # 1.9e13: clashes at the start
+    assert r["energy"] < 1e-6 * e0
