@@ -121,14 +121,16 @@ def cpu_baseline(system, x0, seconds: float = 15.0):
 def batch_bench(args):
     """The many-systems workload: 256 independent chains with sizes log-uniform
     in [200, 4000] atoms (seeds 100..355), minimized together by L-BFGS (m = 10)
-    in one ff_minimize call on an autotuned tiling, to |grad E|_inf < 1e-3 or
-    --batch-iters iterations (default 60,000).  Reports the wall time per system from the start points
+    in one ff_minimize call to |grad E|_inf < 1e-3 or --batch-iters iterations
+    (default 60,000).  Reports the wall time per system from the start points
     resident in HBM to the certified results.
 
-    The tiling is tuned on FP64 evaluations whatever the minimization's mode:
-    runs to 1e-3 in FP32 mode spend about nine in ten evaluations in FP64
-    after the end-game switch, and FP64 timings do not depend on how
-    clash-ridden the start point is (FP32 ones do: its close-pair paths)."""
+    The tiling is the library's default for batches (64-atom I-blocks, chunks
+    of 4 j-tiles in both kernels), which ran faster per evaluation than what
+    the autotuner picks from timings at the start points; --batch-autotune
+    tunes the FP64 kernel's configuration and chunk length (runs to 1e-3
+    spend about nine in ten evaluations in FP64) and, in FP32 mode, the FP32
+    kernel's chunk length for the same configuration."""
     import numpy as np
     import torch
     import paper_1810_03358_amd as ff
@@ -140,8 +142,17 @@ def batch_bench(args):
     x0 = torch.tensor(np.concatenate([s["x"] for s in systems]), dtype=torch.float64, device=dev).contiguous()
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
-        tiling, tune_ms = ff.autotune(systems, x0, "fp64", reps=3, stream=stream)
+        tiling, tune_ms = None, None
+        if args.batch_autotune:
+            (cfg, chunk64), tune_ms = ff.autotune(systems, x0, "fp64", reps=3, stream=stream)
+            chunk = chunk64
+            if args.precision == "fp32":
+                (cfg32, chunk32), _ = ff.autotune(systems, x0, "fp32", reps=3, stream=stream)
+                if cfg32 == cfg:
+                    chunk = chunk32
+            tiling = (cfg, chunk, chunk64)
         ctx = ff.Context(systems, m_max=10, device=dev, stream=stream, tiling=tiling)
+        tiling = ctx.tiling
         x = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -170,6 +181,7 @@ def batch_bench(args):
         "iters_median": float(np.median(iters)), "iters_max": int(iters.max()),
         "evals_total": int(evals), "evals_fp64_total": int(sum(r["evals_fp64"] for r in res)),
         "system_evals_per_s": evals / wall,
+        "tiling_source": "autotuned" if args.batch_autotune else "library default",
         "autotune_ms_per_fp64_batch_eval": tune_ms,
     }
     print(json.dumps(out), flush=True)
@@ -423,6 +435,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=60_000, help="batch256: iteration limit per system")
+    ap.add_argument("--batch-autotune", action="store_true",
+                    help="batch256: autotune the tiling instead of the library default")
     ap.add_argument("--solve", action="store_true",
                     help="chain512/10k/50k: minimize to |grad E|_inf < 1e-3 and report the time instead")
     ap.add_argument("--solve-iters", type=int, default=100_000, help="--solve: iteration limit")
