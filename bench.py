@@ -125,9 +125,10 @@ def batch_bench(args):
     (default 60,000).  Reports the wall time per system from the start points
     resident in HBM to the certified results.
 
-    The tiling is the library's default for batches (64-atom I-blocks, chunks
-    of 4 j-tiles in both kernels), which ran faster per evaluation than what
-    the autotuner picks from timings at the start points; --batch-autotune
+    The tiling is the library's default for batches (128-atom I-blocks with
+    two atoms per lane, chunks of 4 j-tiles in both kernels), which ran
+    faster per evaluation than what the autotuner picks from timings at the
+    start points; --batch-autotune
     tunes the FP64 kernel's configuration and chunk length (runs to 1e-3
     spend about nine in ten evaluations in FP64) and, in FP32 mode, the FP32
     kernel's chunk length for the same configuration."""

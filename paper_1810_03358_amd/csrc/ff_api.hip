@@ -159,7 +159,10 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     L.n_sys = n_sys;
     // defaults from sweeps of whole FP32 and FP64 evaluations on MI355X
     // (2,048 to 50,000 atoms, configurations x chunk lengths 1 to 16, per
-    // precision): batches and systems up to 6,144 atoms use 64-atom blocks;
+    // precision): batches use 128-atom blocks with two atoms per lane in both
+    // kernels (the 256-chain batch of 200-4,000 atoms: 4 % less per FP64
+    // evaluation than with 64-atom blocks, 2 % more per FP32 one); systems up
+    // to 6,144 atoms use 64-atom blocks;
     // up to 12,288 atoms 256-atom blocks with one atom per lane (enough
     // workgroups to fill the chip); above, two atoms per lane in FP32 and four
     // in FP64.  The FP64 kernel, with fewer and longer-lived wavefronts,
@@ -168,7 +171,7 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     // per FP64 evaluation at 50k atoms), the FP32 kernel from two j-tiles
     // only above 32,768 atoms
     auto pick = [&](int cfg, int c32, int c64) { L.cfg = cfg; L.chunk[0] = c32; L.chunk[1] = c64; };
-    if (n_sys > 1) pick(0, 4, 4);
+    if (n_sys > 1) pick(9, 4, 4);
     else if (n_max <= 6144) pick(0, 1, 1);
     else if (n_max < 12288) pick(1, 1, 2);
     else if (n_max < 20000) pick(8, 1, 1);

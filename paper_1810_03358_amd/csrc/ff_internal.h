@@ -170,6 +170,7 @@ constexpr TileConfig kTileConfigs[] = {
     {128, 1, 2, 2, 1},    // 6
     {256, 2, 2, 2, 2},    // 7: as 4, with two atoms per lane in FP64 too
     {256, 2, 2, 1, 4},    // 8: as 4, with four atoms per lane in FP64
+    {128, 1, 2, 1, 2},    // 9: as 6, with two atoms per lane in FP64 too
 };
 constexpr int kNumTileConfigs = sizeof(kTileConfigs) / sizeof(kTileConfigs[0]);
 

@@ -694,6 +694,7 @@ hipError_t launch_pair(const Args& a, int prec, hipStream_t s) {
         FF_PAIR_CASE(6)
         FF_PAIR_CASE(7)
         FF_PAIR_CASE(8)
+        FF_PAIR_CASE(9)
     default:
         return hipErrorInvalidValue;
     }
