@@ -162,19 +162,22 @@ static bool make_layout(const ff_system* s, int32_t n_sys, int32_t m_max, Layout
     // precision): batches use 128-atom blocks with two atoms per lane in both
     // kernels (the 256-chain batch of 200-4,000 atoms: 4 % less per FP64
     // evaluation than with 64-atom blocks, 2 % more per FP32 one); systems up
-    // to 6,144 atoms use 64-atom blocks;
-    // up to 12,288 atoms 256-atom blocks with one atom per lane (enough
-    // workgroups to fill the chip); above, two atoms per lane in FP32 and four
-    // in FP64.  The FP64 kernel, with fewer and longer-lived wavefronts,
-    // gains from longer chunks as the system grows (two j-tiles from 20,000
-    // atoms, four from 32,768, eight from 45,000 on: 1.49 instead of 1.55 ms
-    // per FP64 evaluation at 50k atoms), the FP32 kernel from two j-tiles
-    // only above 32,768 atoms
+    // to 1,024 atoms 64-atom blocks; up to 12,288 atoms 256-atom blocks with
+    // one atom per lane (enough workgroups to fill the chip); up to 20,000
+    // atoms 128-atom blocks with two atoms per lane (15k atoms: 5 % less per
+    // evaluation than 256-atom blocks); above, 256-atom blocks with two atoms
+    // per lane in FP32 and four in FP64.  The FP64 kernel, with fewer and
+    // longer-lived wavefronts, gains from longer chunks as the system grows
+    // (two j-tiles from 6,145 atoms up to 12,287 and from 20,000, four from
+    // 32,768, eight from 45,000 on: 1.49 instead of 1.55 ms per FP64
+    // evaluation at 50k atoms), the FP32 kernel from two j-tiles only above
+    // 32,768 atoms
     auto pick = [&](int cfg, int c32, int c64) { L.cfg = cfg; L.chunk[0] = c32; L.chunk[1] = c64; };
     if (n_sys > 1) pick(9, 4, 4);
-    else if (n_max <= 6144) pick(0, 1, 1);
+    else if (n_max <= 1024) pick(0, 1, 1);
+    else if (n_max <= 6144) pick(1, 1, 1);
     else if (n_max < 12288) pick(1, 1, 2);
-    else if (n_max < 20000) pick(8, 1, 1);
+    else if (n_max < 20000) pick(9, 1, 1);
     else if (n_max < 32768) pick(8, 1, 2);
     else if (n_max < 45000) pick(8, 2, 4);
     else pick(8, 2, 8);

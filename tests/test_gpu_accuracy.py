@@ -8,7 +8,8 @@ error relative to |grad E|_inf.  Gates: energy 1e-6 and gradient norms 1e-5
 relative in both modes (FP32 mode: where |grad E|_inf >= 1, as elsewhere);
 largest component error relative to |grad E|_inf: 1e-12 in FP64 mode and
 RC_FP32 in FP32 mode, a constant calibrated once on chain512 (start and
-relaxed point: at most 1.4e-6 measured) and frozen at about three times
+relaxed point: at most 1.4e-6 measured; 2.1e-6 with a later default
+tiling, whose summation order reaches another 300-iteration point) and frozen at about three times
 that.  The printed table is the measured error (run with -s to see it).
 """
 import numpy as np
