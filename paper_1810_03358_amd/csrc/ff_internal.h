@@ -17,7 +17,6 @@
 
 namespace ff {
 
-constexpr int kAtomAlign = 512;      // single-system padding (largest I-block)
 constexpr int kTile = 64;            // j-tile: one atom per lane of a wavefront
 constexpr int kExclWindow = 64;      // exclusions of this reach live in a per-atom bitmask;
                                      // farther ones in per-unit masks (far units)
