@@ -50,6 +50,22 @@ def abs_pair_force_sum(s, x):
     return (f * mask).sum(1)
 
 
+# FP32 mode, element by element: |g - g_ref| per component against
+# sum_j |f_ij| of the atom (the size of the pair forces its FP32 tile sums add
+# up).  Calibrated once over the energy and tiling tests (65-10,000 atoms,
+# every tile configuration and chunk length): at most 1.33e-6 measured; frozen
+# at 2^-18 (about three times that).  Plus 1e-9 |grad E|_inf for atoms whose
+# pairs are all excluded.
+FP32_ELEM = 2.0 ** -18
+
+
+def fp32_elem_ratio(g, g_ref, pfs):
+    """Largest component error relative to the atom's sum_j |f_ij| (atoms with
+    non-excluded pairs only)."""
+    m = pfs[:, 0] > 0
+    return float(np.max(np.abs(g - g_ref)[m] / pfs[m])) if m.any() else 0.0
+
+
 def check(s, x, prec, fp64_elem=1e-11):
     e_ref, g_ref = oracle.energy_grad(s, np.asarray(x).reshape(-1, 3))
     e, g = gpu_eval(s, x, prec)
@@ -62,7 +78,9 @@ def check(s, x, prec, fp64_elem=1e-11):
         assert np.abs(g - g_ref).max() <= fp64_elem * max(nir, 1e-300)
         assert abs(e - e_ref) <= 1e-11 * max(scale, 1.0)
     else:
-        bound = 2.0 ** -16 * abs_pair_force_sum(s, x)[:, None] + 1e-9 * nir
+        pfs = abs_pair_force_sum(s, x)[:, None]
+        bound = FP32_ELEM * pfs + 1e-9 * nir
+        print(f"fp32 element ratio {fp32_elem_ratio(g, g_ref, pfs):.3e} n={len(g)}")
         assert np.all(np.abs(g - g_ref) <= bound), np.abs(g - g_ref).max()
         if nir >= 1.0:
             assert abs(n2 - n2r) <= 1e-5 * n2r and abs(ni - nir) <= 1e-5 * nir
