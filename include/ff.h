@@ -244,9 +244,9 @@ ff_status ff_energy_grad(ff_ctx *ctx, const double *xyz, double *energy, double 
  *    can overlap another call's on the same GPU (other streams, other
  *    threads) races with it.
  *  - A system whose workspace exceeds FF_NOALLOC_SCRATCH_BYTES (chains of up
- *    to about 20,000 atoms fit) gives FF_ERR_UNSUPPORTED before any device
+ *    to about 23,000 atoms fit) gives FF_ERR_UNSUPPORTED before any device
  *    work; other errors as for ff_create and ff_energy_grad. */
-#define FF_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define FF_NOALLOC_SCRATCH_BYTES (128u << 20)
 ff_status ff_energy_grad_noalloc(const ff_system *sys, const double *xyz, double *energy, double *grad,
                                  int32_t precision, void *stream);
 

@@ -15,7 +15,7 @@ FF_CONVERGED, FF_MAX_ITER, FF_LS_FAILED, FF_NONFINITE_START, FF_DIVERGED = 0, 1,
 FF_LS_DEFAULT, FF_LS_PAR, FF_LS_H = -1, 0, 1
 FF_MIN_RESUME, FF_MIN_NO_CERTIFY = 1, 2
 FF_CG_PRP, FF_CG_FR, FF_CG_HS, FF_CG_PRP_PLUS, FF_CG_CD, FF_CG_LS, FF_CG_DY = 0, 1, 2, 3, 4, 5, 6
-FF_NOALLOC_SCRATCH_BYTES = 64 << 20
+FF_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

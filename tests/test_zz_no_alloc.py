@@ -67,3 +67,25 @@ def test_noalloc_matches_the_context_entry_point_on_two_calls(prec):
     e, g = _noalloc(first, prec)
     assert e == results[0][0]
     np.testing.assert_array_equal(g, results[0][1])
+
+
+def test_noalloc_near_the_scratch_limit():
+    """A 22,000-atom chain: its energy-only layout takes most of the static
+    scratch (about 23,000 atoms fit), so the far end of the array is used;
+    the results are those of the context path, bit for bit, in both
+    precisions, then a small system follows."""
+    from synth import chain_system
+    big = chain_system(22_000, 13)
+    for prec in ("fp64", "fp32"):
+        print(f"noalloc {prec} n={big['n_atoms']}", flush=True)
+        e, g = _noalloc(big, prec)
+        e_c, g_c = _context(big, prec)
+        assert e == e_c
+        np.testing.assert_array_equal(g, g_c)
+    e_ref, g_ref = oracle.energy_grad(big, big["x"])
+    assert abs(e - e_ref) <= 1e-6 * abs(e_ref)
+    small = torsion_chain(300, 14)
+    e, g = _noalloc(small, "fp64")
+    e_c, g_c = _context(small, "fp64")
+    assert e == e_c
+    np.testing.assert_array_equal(g, g_c)
